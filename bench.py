@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Benchmark of the short-range PP gravity path on one MI355X.
+
+One step = the whole path on one box resident in HBM: Peano-Hilbert keys,
+key sort and gather, octree leaves, near lists, the FP32 PP kernel and the
+scatter back to input order (pp_accel).  The workload is the plain-kernel
+headline set: 128^3 = 2,097,152 equal-mass particles in a periodic box of
+200 Mpc/h, half uniform and half in 2000 Plummer spheres (dN/dM ~ M^-1.9),
+PM mesh 128^3, r_s = 1.25 cells, r_cut = 4.5 r_s, eps = 0.02 cells.
+
+Prints one JSON line.  value = interactions (ordered pairs with s < r_cut)
+per second of whole steps.  roofline: the PP kernel's FP32 flop rate (its
+stated per-interaction count x interactions / kernel time from HIP events
+on the launch stream) against the FP32 vector peak.  cpu_baseline: the FP64
+CPU oracle timed on this host on a bounded sample of targets.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PP pair-interactions/s and % FP32 VALU peak; batched vs plain at fixed error"
+# FP32 operations the PP kernel performs per evaluated pair (an FMA counts 2):
+# 3 sub (d), 3 FMA (s^2 + eps^2), 1 rsqrt, 1 FMA (polynomial variable),
+# 9 FMA (polynomial), 1 mul + 1 FMA (y^3 - k^3 H), 1 mul (mass), 3 FMA (sum).
+FLOPS_PER_INTERACTION = 40
+PAPER_FLOPS_PER_INTERACTION = 22      # convention of sec. 5 (Newtonian pair count)
+FP32_VECTOR_PEAK = 157.3e12           # MI355X, 256 CU x 2.4 GHz x 256 flop/clk
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def nearest_rank(x, q):
+    import numpy as np
+    x = np.sort(np.asarray(x))
+    if x.size == 0:
+        return 0.0
+    return float(x[max(1, int(math.ceil(q / 100.0 * x.size))) - 1])
+
+
+def cpu_baseline(box, acc_gpu, budget_s):
+    """Time the FP64 oracle on a seeded sample of targets; compare the GPU
+    accelerations of the same targets."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(1802)
+    mass64 = box.mass.astype(np.float64)
+    probe = np.sort(rng.choice(box.n, 64, replace=False))
+    t0 = time.perf_counter()
+    oracle.accel(box.pos, mass64, box.params, targets=probe)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    k = int(min(box.n, max(256, 64 * budget_s / dt)))
+    targets = np.sort(rng.choice(box.n, k, replace=False))
+    t0 = time.perf_counter()
+    ref = oracle.accel(box.pos, mass64, box.params, targets=targets)
+    sec = time.perf_counter() - t0
+    inter = int(ref["n_inter"].sum())
+    a = acc_gpu[:, targets].astype(np.float64)
+    r = ref["acc"]
+    cands = [r, r - ref["band_in"] + ref["band_out"], r - ref["band_in"], r + ref["band_out"]]
+    err = np.min([np.linalg.norm(a - c, axis=0) for c in cands], axis=0)
+    norm = np.linalg.norm(r, axis=0)
+    has = ref["n_inter"] > 0
+    e = err[has] / norm[has]
+    base = {"value": inter / sec, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{k} seeded random targets of the same box against all {box.n} sources "
+                      f"(FP64 direct sum, {inter} interactions, {sec:.1f} s)"}
+    errs = {"targets": int(has.sum()), "median": nearest_rank(e, 50), "p999": nearest_rank(e, 99.9),
+            "max": float(e.max()) if e.size else 0.0,
+            "zero_neighbour_exact": bool(np.all(a[:, ~has] == 0))}
+    return base, errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is a single-GPU "
+              "kernel library and has no multi-GPU mode.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1802_09824_amd as pp
+
+    box = workloads.make_config(2)
+    p = box.params
+    pos = torch.tensor(box.pos, device="cuda")
+    mass = torch.tensor(box.mass, device="cuda")
+    acc = torch.empty((3, box.n), dtype=torch.float32, device="cuda")
+    plan = pp.Plan(p, box.n)
+    plan.accel(pos, mass, out=acc)
+    interactions = plan.count_interactions()
+    for _ in range(args.warmup):
+        plan.accel(pos, mass, out=acc)
+    plan.set_timing(True)
+    kernel_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.accel(pos, mass, out=acc)
+        kernel_ms.append(plan.stats()["pp_kernel_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = plan.stats()
+    ms_step = 1e3 * elapsed / args.steps
+    value = interactions * args.steps / elapsed
+    k_ms = float(np.mean(kernel_ms))
+    achieved = interactions * FLOPS_PER_INTERACTION / (k_ms * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": box.name, "n": box.n, "L": p.L, "n_mesh": 128, "rs": p.rs,
+                   "rcut": p.rcut, "eps": p.eps, "G": p.G, "leaf_max": p.leaf_max,
+                   "clustered_fraction": 0.5, "spheres": 2000, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                     "kernel": "pp_f32_kernel", "kernel_ms": k_ms,
+                     "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "interactions_per_step": interactions,
+        "candidates_per_step": int(st["candidates"]),
+        "pp_kernel_interactions_per_s": interactions / (k_ms * 1e-3),
+        "pct_fp32_peak_paper_22flop": 100.0 * interactions * PAPER_FLOPS_PER_INTERACTION
+        / (k_ms * 1e-3) / FP32_VECTOR_PEAK,
+        "lists": {k: int(st[k]) for k in ("nleaf", "nblock", "nrange", "nitem")},
+    }
+    if not args.no_cpu_baseline:
+        base, errs = cpu_baseline(box, acc.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = base
+        out["error_vs_oracle"] = errs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * photon_pp — short-range particle-particle (PP) gravity on one MI355X GPU.
+ *
+ * The hot path of a PM + Tree + PP N-body solver (Wang et al. 2018,
+ * "PHoToNs", arXiv:1802.09824): for every particle i of a periodic box,
+ *
+ *   a_i = sum_{j != i, s_ij < r_cut}  G m_j d_ij g(s_eps / (2 r_s)) / s_eps^3
+ *
+ * with d_ij = x_j - x_i at the minimum periodic image, s = |d_ij|,
+ * s_eps = sqrt(s^2 + eps^2) (Plummer softening), and g the short-range factor
+ * of the Gaussian PM split, sec. 3.1 Eq. (equ:split):
+ *   g(x) = erfc(x) + (2 x / sqrt(pi)) exp(-x^2).
+ * The pairs are found the way sec. 3.2-3.3 organise them: particles are
+ * sorted along a Peano-Hilbert curve (sec. 4.1) so every octree node is one
+ * contiguous run (sec. 3.2), leaves are nodes of at most leaf_max particles
+ * (sec. 3.3, "a leaf is a package"), and the PP kernel runs over near
+ * leaf pairs (the N-to-M case of the dual tree traversal, sec. 3.3).
+ *
+ * Conventions for every call:
+ *  - return value: PP_OK (0) or a negative pp_status; nothing throws;
+ *    pp_last_error() returns a message for the calling thread's last error.
+ *  - buffers: device pointers owned by the caller, unless stated otherwise.
+ *    Export calls accept host or device destinations.
+ *  - layout: positions and accelerations are SoA [3][n] (x block, then y,
+ *    then z), float64 positions, float32 masses/accelerations (float64 for
+ *    the _f64 calls).
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it.  Calls that must size library-owned buffers read a
+ *    count back and therefore synchronise that stream; each says so.
+ *  - objects: the library owns pp_leaves, pp_pairs, pp_plan and
+ *    pp_batch_plan; free them with the matching *_free / *_destroy.
+ *  - one object must not be used from two threads at once.
+ */
+#ifndef PHOTON_PP_H
+#define PHOTON_PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pp_status {
+    PP_OK = 0,
+    PP_EINVAL = -1,     /* bad argument (size, pointer, parameter, NaN/Inf input) */
+    PP_ENOMEM = -2,     /* device or host allocation failed */
+    PP_EDEVICE = -3,    /* HIP runtime error (no device, launch failure, ...) */
+    PP_ERANGE = -4,     /* parameter outside the supported range (e.g. r_cut >= L/2) */
+    PP_EOVERFLOW = -5   /* caller buffer too small; the needed size is reported */
+} pp_status;
+
+/* Per-box parameters.  Lengths in any unit, consistent with the positions.
+ *  L        periodic box side, > 0
+ *  rs       split scale r_s of the PM/PP force split (sec. 3.1), > 0
+ *  rcut     hard cut radius of the short-range sum, 0 < rcut < L/2 (so one
+ *           periodic image at most lies within it); sec. 3.1 uses 4.5 r_s.
+ *           The FP32 kernel's split-factor polynomial covers
+ *           sqrt(rcut^2 + eps^2) <= 4.52 r_s; beyond that PP_ERANGE.
+ *  eps      Plummer softening length, >= 0
+ *  G        gravitational constant (any finite value)
+ *  leaf_max maximum particles per octree leaf, 1..1024 (a leaf at the
+ *           finest key level may hold more: its particles share a cell)
+ *  key_bits bits per axis of the Peano-Hilbert grid, 1..21               */
+typedef struct pp_box_params {
+    double L, rs, rcut, eps, G;
+    int32_t leaf_max, key_bits;
+} pp_box_params;
+
+typedef struct pp_leaves pp_leaves;
+typedef struct pp_pairs pp_pairs;
+typedef struct pp_plan pp_plan;
+typedef struct pp_batch_plan pp_batch_plan;
+
+/* Peano-Hilbert keys, sec. 4.1 (a 2^(3b) grid labelled along the curve).
+ * Each coordinate is wrapped, w = x - L floor(x / L), and quantised,
+ * q = floor(w * (2^b / L)) clamped to [0, 2^b - 1]; the key is the index of
+ * cell q along J. Skilling's Hilbert curve ("Programming the Hilbert
+ * curve", 2004), x taking the most significant bit of every 3-bit digit.
+ *   pos   device SoA [3][n] float64;  keys  device [n] uint64 (out)
+ * Errors: PP_EINVAL for n < 0, NULL pointers with n > 0, L <= 0, b out of
+ * 1..21.  Asynchronous.                                                   */
+int pp_hilbert_keys(const double* pos, int64_t n, double L, int key_bits,
+                    uint64_t* keys, void* stream);
+
+/* Scratch bytes pp_sort_by_key needs for n keys. */
+int pp_sort_workspace_size(int64_t n, size_t* bytes);
+
+/* Stable sort by key (sec. 3.2: all particles of a tree node become one
+ * contiguous run).  Equal keys keep their input order, so the order is by
+ * (key, index).  perm[k] is the input index of the k-th particle in key
+ * order; sorted_keys (may be NULL) receives keys[perm[k]].
+ *   keys device [n] uint64; perm device [n] int32 (out); ws device scratch
+ *   of at least pp_sort_workspace_size(n) bytes.
+ * Errors: PP_EINVAL (n < 0 or n > 2^31 - 1, NULL pointers), PP_EOVERFLOW
+ * if ws_bytes is too small.  Asynchronous.                                 */
+int pp_sort_by_key(const uint64_t* keys, int64_t n, int32_t* perm, uint64_t* sorted_keys,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Octree leaves (sec. 3.2-3.3): maximal octree nodes holding at most
+ * leaf_max particles, each a contiguous run of the key-sorted particles.
+ * A node at level l is the set of particles sharing the top 3 l key bits.
+ *   sorted_keys  device [n] uint64, ascending
+ *   pos_sorted   device SoA [3][n] float64, the same particles in key order
+ *                (used for the integer bounding boxes)
+ *   p            box parameters (L, key_bits, leaf_max are used)
+ *   out          receives a library-owned pp_leaves
+ * Synchronises the stream (reads the leaf count back).
+ * Errors: PP_EINVAL (bad sizes/params), PP_ENOMEM, PP_EDEVICE.             */
+int pp_build_leaves(const uint64_t* sorted_keys, const double* pos_sorted, int64_t n,
+                    const pp_box_params* p, pp_leaves** out, void* stream);
+int pp_leaves_count(const pp_leaves* lv, int64_t* nleaf);
+/* Copy the leaf table out (host or device destinations; any may be NULL):
+ * begin [m] int64, count [m] int32, level [m] int32, prefix [m] uint64 (the
+ * top 3*level key bits), lo/hi [3][m] int32 integer bounding box of the
+ * particles' grid cells, hi exclusive (max q + 1).  Synchronous.           */
+int pp_leaves_export(const pp_leaves* lv, int64_t* begin, int32_t* count, int32_t* level,
+                     uint64_t* prefix, int32_t* lo, int32_t* hi);
+void pp_leaves_free(pp_leaves* lv);
+
+/* Near leaf pairs: the N-to-M leaf pairs of the dual tree traversal
+ * (sec. 3.3) restricted to the short range.  In grid units (the box is
+ * W = 2^b cells wide) target leaf A, source leaf B and periodic shift
+ * s in {-1,0,1}^3 form a pair iff
+ *   sum_k max(0, lo_B,k + s_k W - hi_A,k, lo_A,k - hi_B,k - s_k W)^2 < T,
+ *   T = ceil(r^2),  r = rcut * W / L  (FP64, this operation order).
+ * Every particle pair closer than rcut therefore appears.  Rows are target
+ * leaves in key order; within a row entries ascend by (B, code) with
+ * code = 9 (s_x + 1) + 3 (s_y + 1) + (s_z + 1).
+ * Synchronises the stream (reads the entry count back).                    */
+int pp_near_pairs(const pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* stream);
+int pp_pairs_count(const pp_pairs* pr, int64_t* nrows, int64_t* nentries);
+/* Copy the canonical CSR out: row_ptr [nrows + 1] int64, src_leaf
+ * [nentries] int32, shift_code [nentries] uint8.  Synchronous.             */
+int pp_pairs_export(const pp_pairs* pr, int64_t* row_ptr, int32_t* src_leaf, uint8_t* shift_code);
+void pp_pairs_free(pp_pairs* pr);
+
+/* A plan validates the parameters, owns all scratch memory for boxes of
+ * up to n_max particles and holds the kernel tiling.
+ * Errors: PP_EINVAL / PP_ERANGE for parameters, PP_ENOMEM, PP_EDEVICE.     */
+int pp_plan_create(const pp_box_params* p, int64_t n_max, pp_plan** out);
+void pp_plan_destroy(pp_plan* plan);
+
+/* Short-range accelerations (the whole path: keys, sort, leaves, near
+ * lists, FP32 PP kernel, scatter back to input order).
+ *   pos  device SoA [3][n] float64, input order, any values (wrapped)
+ *   mass device [n] float32;  acc device SoA [3][n] float32 (out)
+ * Arithmetic: positions relative to a per-block FP64 origin are rounded to
+ * FP32; pair arithmetic is FP32 with a compensated per-target sum.
+ * Synchronises the stream (list sizes).  PP_EINVAL for n > n_max, NaN/Inf
+ * positions or masses.                                                     */
+int pp_accel(pp_plan* plan, const double* pos, const float* mass, int64_t n, float* acc,
+             void* stream);
+
+/* The same sum entirely in FP64 (accuracy yardstick).                     */
+int pp_accel_f64(pp_plan* plan, const double* pos, const double* mass, int64_t n, double* acc,
+                 void* stream);
+
+/* Figures of the last pp_accel / pp_accel_f64 / pp_count_interactions call. */
+typedef struct pp_stats {
+    int64_t n, nleaf, nblock, nrange, nitem;
+    int64_t candidates;     /* (target, source) evaluations incl. masked ones */
+    int64_t interactions;   /* pairs with s < rcut, j != i (set by pp_count_interactions), else -1 */
+    double pp_kernel_ms;    /* duration of the last PP kernel launch (HIP events on the
+                               caller's stream) when timing is on, else -1 */
+} pp_stats;
+/* Waits for the last PP kernel when timing is on.                          */
+int pp_plan_stats(pp_plan* plan, pp_stats* out);
+
+/* Turn HIP-event timing of the PP kernel on (1) or off (0).                */
+int pp_plan_set_timing(pp_plan* plan, int on);
+
+/* Count, per target, the pairs with s < rcut and j != i (FP64 test), using
+ * the plan's lists from the last pp_accel call on the same positions.
+ *   counts device [n] int64 (out, input order; may be NULL) ; total (host).
+ * Synchronises the stream.                                                 */
+int pp_count_interactions(pp_plan* plan, int64_t* counts, int64_t* total, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHOTON_PP_H */

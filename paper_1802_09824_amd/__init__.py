@@ -1,0 +1,250 @@
+"""photon_pp: short-range PP gravity on one MI355X GPU (Python binding).
+
+A thin ctypes layer over libphoton_pp.so (C ABI in include/photon_pp.h).
+It only marshals arguments: every stage of the path runs in the library's
+HIP kernels.  Torch is used for device memory and the current stream.
+If the library has not been built the import fails loudly; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphoton_pp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1802_09824_amd/build.py` "
+                      "(hipcc, gfx950); there is no CPU fallback")
+_lib = C.CDLL(LIB_PATH)
+
+PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ERANGE, PP_EOVERFLOW = 0, -1, -2, -3, -4, -5
+
+
+class PPError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.pp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.pp_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+class pp_box_params(C.Structure):
+    _fields_ = [("L", C.c_double), ("rs", C.c_double), ("rcut", C.c_double), ("eps", C.c_double),
+                ("G", C.c_double), ("leaf_max", C.c_int32), ("key_bits", C.c_int32)]
+
+
+class pp_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nleaf", C.c_int64), ("nblock", C.c_int64),
+                ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
+                ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double)]
+
+
+_P, _i64, _i32, _dbl, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_size_t
+_SIGS = {
+    "pp_strerror": (C.c_char_p, [_i32]),
+    "pp_last_error": (C.c_char_p, []),
+    "pp_hilbert_keys": (_i32, [_P, _i64, _dbl, _i32, _P, _P]),
+    "pp_sort_workspace_size": (_i32, [_i64, C.POINTER(_sz)]),
+    "pp_sort_by_key": (_i32, [_P, _i64, _P, _P, _P, _sz, _P]),
+    "pp_build_leaves": (_i32, [_P, _P, _i64, C.POINTER(pp_box_params), C.POINTER(_P), _P]),
+    "pp_leaves_count": (_i32, [_P, C.POINTER(_i64)]),
+    "pp_leaves_export": (_i32, [_P, _P, _P, _P, _P, _P, _P]),
+    "pp_leaves_free": (None, [_P]),
+    "pp_near_pairs": (_i32, [_P, C.POINTER(pp_box_params), C.POINTER(_P), _P]),
+    "pp_pairs_count": (_i32, [_P, C.POINTER(_i64), C.POINTER(_i64)]),
+    "pp_pairs_export": (_i32, [_P, _P, _P, _P]),
+    "pp_pairs_free": (None, [_P]),
+    "pp_plan_create": (_i32, [C.POINTER(pp_box_params), _i64, C.POINTER(_P)]),
+    "pp_plan_destroy": (None, [_P]),
+    "pp_accel": (_i32, [_P, _P, _P, _i64, _P, _P]),
+    "pp_accel_f64": (_i32, [_P, _P, _P, _i64, _P, _P]),
+    "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
+    "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
+    "pp_plan_set_timing": (_i32, [_P, _i32]),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc: int, where: str):
+    if rc != PP_OK:
+        raise PPError(rc, where)
+
+
+def make_params(p) -> pp_box_params:
+    """pp_box_params from any object with L, rs, rcut, eps, G, leaf_max, key_bits."""
+    return pp_box_params(float(p.L), float(p.rs), float(p.rcut), float(p.eps), float(p.G),
+                         int(getattr(p, "leaf_max", 32)), int(getattr(p, "key_bits", 21)))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def pp_hilbert_keys(pos: torch.Tensor, L: float, key_bits: int = 21, stream=None) -> torch.Tensor:
+    n = pos.shape[1]
+    keys = torch.empty(n, dtype=torch.int64, device=pos.device)   # bit pattern of uint64
+    _check(_lib.pp_hilbert_keys(_dev(pos, torch.float64, (3, n), "pos"), n, float(L), int(key_bits),
+                                C.c_void_p(keys.data_ptr()), _stream(stream)), "pp_hilbert_keys")
+    return keys
+
+
+def pp_sort_by_key(keys: torch.Tensor, stream=None):
+    """Returns (perm int32, sorted_keys) for keys given as the int64 bit pattern."""
+    n = keys.numel()
+    need = _sz(0)
+    _check(_lib.pp_sort_workspace_size(n, C.byref(need)), "pp_sort_workspace_size")
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=keys.device)
+    perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+    sk = torch.empty(n, dtype=torch.int64, device=keys.device)
+    _check(_lib.pp_sort_by_key(_dev(keys, torch.int64, name="keys"), n, C.c_void_p(perm.data_ptr()),
+                               C.c_void_p(sk.data_ptr()), C.c_void_p(ws.data_ptr()), need.value,
+                               _stream(stream)), "pp_sort_by_key")
+    torch.cuda.current_stream().synchronize()
+    return perm, sk
+
+
+class Leaves:
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.pp_leaves_free(self._h)
+            self._h = C.c_void_p(None)
+
+    @property
+    def count(self) -> int:
+        m = _i64(0)
+        _check(_lib.pp_leaves_count(self._h, C.byref(m)), "pp_leaves_count")
+        return int(m.value)
+
+    def export(self) -> dict:
+        import numpy as np
+        m = self.count
+        out = {"begin": np.zeros(m, np.int64), "count": np.zeros(m, np.int32),
+               "level": np.zeros(m, np.int32), "prefix": np.zeros(m, np.uint64),
+               "lo": np.zeros((3, m), np.int32), "hi": np.zeros((3, m), np.int32)}
+        _check(_lib.pp_leaves_export(self._h, *(a.ctypes.data_as(_P) for a in out.values())),
+               "pp_leaves_export")
+        return out
+
+
+def pp_build_leaves(sorted_keys: torch.Tensor, pos_sorted: torch.Tensor, params, stream=None) -> Leaves:
+    n = sorted_keys.numel()
+    h = _P(None)
+    prm = make_params(params)
+    _check(_lib.pp_build_leaves(_dev(sorted_keys, torch.int64, name="sorted_keys"),
+                                _dev(pos_sorted, torch.float64, (3, n), "pos_sorted"), n,
+                                C.byref(prm), C.byref(h), _stream(stream)), "pp_build_leaves")
+    return Leaves(h.value)
+
+
+class Pairs:
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.pp_pairs_free(self._h)
+            self._h = C.c_void_p(None)
+
+    def export(self):
+        import numpy as np
+        nr, ne = _i64(0), _i64(0)
+        _check(_lib.pp_pairs_count(self._h, C.byref(nr), C.byref(ne)), "pp_pairs_count")
+        rp = np.zeros(nr.value + 1, np.int64)
+        src = np.zeros(max(ne.value, 1), np.int32)
+        code = np.zeros(max(ne.value, 1), np.uint8)
+        _check(_lib.pp_pairs_export(self._h, rp.ctypes.data_as(_P), src.ctypes.data_as(_P),
+                                    code.ctypes.data_as(_P)), "pp_pairs_export")
+        return rp, src[:ne.value], code[:ne.value]
+
+
+def pp_near_pairs(leaves: Leaves, params, stream=None) -> Pairs:
+    h = _P(None)
+    prm = make_params(params)
+    _check(_lib.pp_near_pairs(leaves._h, C.byref(prm), C.byref(h), _stream(stream)), "pp_near_pairs")
+    return Pairs(h.value)
+
+
+class Plan:
+    """pp_plan: parameters, scratch memory for up to n_max particles."""
+
+    def __init__(self, params, n_max: int):
+        self.params = params
+        self.n_max = int(n_max)
+        h = _P(None)
+        prm = make_params(params)
+        _check(_lib.pp_plan_create(C.byref(prm), self.n_max, C.byref(h)), "pp_plan_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.pp_plan_destroy(self._h)
+            self._h = C.c_void_p(None)
+
+    def accel(self, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        n = pos.shape[1]
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+        _check(_lib.pp_accel(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                             _dev(mass, torch.float32, (n,), "mass"), n,
+                             _dev(out, torch.float32, (3, n), "acc"), _stream(stream)), "pp_accel")
+        return out
+
+    def accel_f64(self, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+        n = pos.shape[1]
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        _check(_lib.pp_accel_f64(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                 _dev(mass, torch.float64, (n,), "mass"), n,
+                                 _dev(out, torch.float64, (3, n), "acc"), _stream(stream)),
+               "pp_accel_f64")
+        return out
+
+    def stats(self) -> dict:
+        st = pp_stats()
+        _check(_lib.pp_plan_stats(self._h, C.byref(st)), "pp_plan_stats")
+        return {k: getattr(st, k) for k, _ in pp_stats._fields_}
+
+    def set_timing(self, on: bool = True):
+        _check(_lib.pp_plan_set_timing(self._h, 1 if on else 0), "pp_plan_set_timing")
+
+    def count_interactions(self, per_target: bool = False, stream=None):
+        tot = _i64(0)
+        counts = None
+        ptr = C.c_void_p(None)
+        if per_target:
+            n = self.stats()["n"]
+            counts = torch.zeros(n, dtype=torch.int64, device="cuda")
+            ptr = C.c_void_p(counts.data_ptr())
+        _check(_lib.pp_count_interactions(self._h, ptr, C.byref(tot), _stream(stream)),
+               "pp_count_interactions")
+        return (int(tot.value), counts) if per_target else int(tot.value)
+
+
+def pp_plan_create(params, n_max: int) -> Plan:
+    return Plan(params, n_max)
