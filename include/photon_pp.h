@@ -159,7 +159,12 @@ int pp_accel_f64(pp_plan* plan, const double* pos, const double* mass, int64_t n
 /* Figures of the last pp_accel / pp_accel_f64 / pp_count_interactions call. */
 typedef struct pp_stats {
     int64_t n, nleaf, nblock, nrange, nitem;
-    int64_t candidates;     /* (target, source) evaluations incl. masked ones */
+    int64_t candidates;     /* (target, listed source) pairs of the block lists */
+    int64_t evaluated;      /* pairs the FP32 kernel evaluated (listed sources that survive
+                               its bounding-box test, incl. pairs masked by the cut); -1 if
+                               the last call was not pp_accel */
+    int64_t lane_pairs;     /* lane-pair slots the FP32 kernel swept (64 per staged source,
+                               idle lanes of partly filled blocks included); -1 likewise */
     int64_t interactions;   /* pairs with s < rcut, j != i (set by pp_count_interactions), else -1 */
     double pp_kernel_ms;    /* duration of the last PP kernel launch (HIP events on the
                                caller's stream) when timing is on, else -1 */

@@ -39,6 +39,7 @@ class pp_box_params(C.Structure):
 class pp_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("nleaf", C.c_int64), ("nblock", C.c_int64),
                 ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
+                ("evaluated", C.c_int64), ("lane_pairs", C.c_int64),
                 ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double)]
 
 

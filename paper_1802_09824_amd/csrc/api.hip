@@ -117,7 +117,7 @@ struct pp_plan {
     pp_stats st{};
     bool lists_valid = false;
     int64_t last_n = 0;
-    bool timing = false, timed = false;
+    bool timing = false, timed = false, evaluated_valid = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~pp_plan() {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -379,6 +379,7 @@ void pp_plan_destroy(pp_plan* plan) { delete plan; }
 static int prepare(pp_plan* pl, const double* pos, const float* mass_f, const double* mass_d,
                    int64_t n, hipStream_t s) {
     pl->lists_valid = false;
+    pl->evaluated_valid = false;
     PP_HIP(hipMemsetAsync(pl->bad.p, 0, sizeof(int), s));
     PP_TRY(launch_keys(pos, n, pl->p.L, pl->p.key_bits, pl->keys.as<uint64_t>(),
                        pl->iota.as<int32_t>(), pl->bad.as<int>(), s));
@@ -400,8 +401,9 @@ static int prepare(pp_plan* pl, const double* pos, const float* mass_f, const do
     if (bad) return fail(PP_EINVAL, "non-finite position or mass");
     PP_TRY(build_tree(pl->lboxes.as<IBox>(), pl->nleaf, pl->tree_boxes, &pl->tv, s));
     PP_TRY(build_block_lists(pl->pos_s.as<double>(), n, pl->lbegin.as<int64_t>(),
-                             pl->lcount.as<int32_t>(), pl->tv, pl->nleaf, pl->g, pl->chunk, pl->bl,
-                             pl->scan_ws.p, pl->scan_ws_bytes, s));
+                             pl->lcount.as<int32_t>(), pl->tv, pl->nleaf, pl->g, pl->chunk,
+                             pl->p.rcut, pl->bl, pl->scan_ws, s));
+    pl->scan_ws_bytes = pl->scan_ws.bytes;
     pl->st.n = n;
     pl->st.nleaf = pl->nleaf;
     pl->st.nblock = pl->bl.nblock;
@@ -432,9 +434,12 @@ int pp_accel(pp_plan* pl, const double* pos, const float* mass, int64_t n, float
     hipStream_t s = S(stream);
     PP_TRY(prepare(pl, pos, mass, nullptr, n, s));
     PP_TRY(pl->partial.reserve(sizeof(float) * 6 * kBlock * (pl->bl.nitem + 1)));
+    unsigned long long* evald = reinterpret_cast<unsigned long long*>(pl->cnt_total.as<char>() + 8);
+    PP_HIP(hipMemsetAsync(evald, 0, 2 * sizeof(unsigned long long), s));
+    pl->evaluated_valid = true;
     if (pl->timing) PP_HIP(hipEventRecord(pl->ev0, s));
     PP_TRY(launch_pp_f32(pl->bl, pl->pos_s.as<double>(), pl->mass_s.as<float>(), n, pl->p, pl->poly,
-                         pl->chunk, pl->partial.as<float>(), s));
+                         pl->chunk, pl->partial.as<float>(), evald, s));
     if (pl->timing) {
         PP_HIP(hipEventRecord(pl->ev1, s));
         pl->timed = true;
@@ -471,6 +476,14 @@ int pp_plan_stats(pp_plan* pl, pp_stats* out) {
         float ms = 0.f;
         PP_HIP(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
         pl->st.pp_kernel_ms = ms;
+    }
+    pl->st.evaluated = -1;
+    pl->st.lane_pairs = -1;
+    if (pl->evaluated_valid) {
+        unsigned long long h[2] = {0, 0};
+        PP_HIP(hipMemcpy(h, pl->cnt_total.as<char>() + 8, sizeof(h), hipMemcpyDeviceToHost));
+        pl->st.evaluated = (int64_t)h[0];
+        pl->st.lane_pairs = (int64_t)h[1];
     }
     *out = pl->st;
     return PP_OK;

@@ -108,14 +108,29 @@ int build_canonical_pairs(const TreeView& tv, int64_t nleaf, const Geo& g, DevBu
                           DevBuf& row_ptr, DevBuf& src, DevBuf& code, void* scan_ws,
                           size_t scan_ws_bytes, int64_t* nentries, hipStream_t s);
 
-// Target blocks of up to kBlock consecutive particles (key order).
+// Target blocks: runs of at most kBlock consecutive particles (key order)
+// inside one kBlock-particle chunk whose bounding box side stays within
+// r_cut (so FP32 offsets from the block centre stay small).
 constexpr int kBlock = 64;
 struct BlockLists {
-    int64_t nblock = 0, nrange = 0, nitem = 0;
+    int64_t nblock = 0, nrange = 0, nitem = 0, nchunk = 0;
     int64_t candidates = 0;
+    DevBuf ccount;     // int32 [nchunk] blocks per chunk
+    DevBuf coff;       // int64 [nchunk + 1]
+    DevBuf bstart;     // int32 [nblock] first particle
+    DevBuf bcount;     // int32 [nblock] particles (1..kBlock)
     DevBuf box;        // IBox [nblock]
-    DevBuf rcount;     // int32 [nblock] ranges per block
-    DevBuf roff;       // int64 [nblock + 1]
+    int64_t nentry = 0;
+    DevBuf fent_a, fent_b;  // breadth-first entries (block, shift, node)
+    DevBuf fcnt;       // int32 per entry: children / ranges
+    DevBuf foff;       // int64 scan of fcnt
+    DevBuf lmask_e;    // uint64 [nentry] passing leaves of the entry's subtree
+    DevBuf rcnt_e;     // int32 [nentry] ranges per entry
+    DevBuf scnt_e;     // int32 [nentry] listed sources per entry
+    DevBuf roff_e;     // int64 [nentry + 1]
+    DevBuf soff_e;     // int64 [nentry + 1]
+    DevBuf eoff;       // int64 [nblock + 1] first entry of each block
+    DevBuf roff;       // int64 [nblock + 1] first range of each block
     DevBuf rbeg;       // int32 [nrange] first source particle
     DevBuf rpre;       // int32 [nrange] exclusive prefix of lengths in the block list
     DevBuf rcode;      // uint8 [nrange] periodic shift code
@@ -127,8 +142,7 @@ struct BlockLists {
 };
 int build_block_lists(const double* pos_s, int64_t n, const int64_t* leaf_begin,
                       const int32_t* leaf_count, const TreeView& tv, int64_t nleaf, const Geo& g,
-                      int chunk, BlockLists& bl, void* scan_ws, size_t scan_ws_bytes,
-                      hipStream_t s);
+                      int chunk, double rcut, BlockLists& bl, DevBuf& scan_ws, hipStream_t s);
 
 // pp_kernels.hip
 struct PolyF32 {
@@ -140,7 +154,7 @@ struct PolyF32 {
 int make_poly(const pp_box_params& p, PolyF32* out);
 int launch_pp_f32(const BlockLists& bl, const double* pos_s, const float* mass_s, int64_t n,
                   const pp_box_params& p, const PolyF32& poly, int chunk, float* partial,
-                  hipStream_t s);
+                  unsigned long long* counters, hipStream_t s);
 int launch_reduce_f32(const BlockLists& bl, const float* partial, const int32_t* perm, int64_t n,
                       double scale, float* acc, hipStream_t s);
 int launch_pp_f64(const BlockLists& bl, const double* pos_s, const double* mass_s, int64_t n,

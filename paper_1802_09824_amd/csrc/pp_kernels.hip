@@ -48,6 +48,8 @@ struct ItemArgs {
     const int32_t* iblock;
     const int32_t* is0;
     int64_t nitem, per_xcd;
+    const int32_t* bstart;
+    const int32_t* bcount;
     const IBox* bbox;
     const int64_t* roff;
     const int32_t* rbeg;
@@ -57,11 +59,74 @@ struct ItemArgs {
     int chunk;
 };
 
+// One source against the lane's target; adds into (tx, ty, tz).
+template <bool NEWTON>
+__device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, float zi,
+                                         const PolyF32& P, float& tx, float& ty, float& tz) {
+    const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
+    float r2 = fmaf(dx, dx, P.eps2n);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    float y = __builtin_amdgcn_rsqf(r2);
+    if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float u = fmaf(r2, P.tscale, -1.f);
+    float h = P.c[9];
+    h = fmaf(h, u, P.c[8]);
+    h = fmaf(h, u, P.c[7]);
+    h = fmaf(h, u, P.c[6]);
+    h = fmaf(h, u, P.c[5]);
+    h = fmaf(h, u, P.c[4]);
+    h = fmaf(h, u, P.c[3]);
+    h = fmaf(h, u, P.c[2]);
+    h = fmaf(h, u, P.c[1]);
+    h = fmaf(h, u, P.c[0]);
+    const float y3 = y * y * y;
+    float F = (y3 - h) * sj.w;
+    F = r2 < P.cut2 ? F : 0.f;
+    tx = fmaf(F, dx, tx);
+    ty = fmaf(F, dy, ty);
+    tz = fmaf(F, dz, tz);
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Orders this wave's LDS accesses around a point (the workgroup is one
+// wave, and a wave's LDS operations complete in issue order, so no
+// s_barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// FP32 PP kernel, one wave per work item (target block, chunk of its
+// source list).  Sources are fetched 64 list positions at a time: each lane
+// maps its position to a particle through the block's ranges (no search when
+// the window lies in one range, else a binary search bounded to 64 ranges
+// from the wave's range cursor) and loads the FP64 position and the mass;
+// the loads of the next window are issued before the current tile is swept.
+// A fetched source is shifted by its periodic image, made relative to the
+// FP64 block centre, scaled by 1/r_cut and rounded to FP32, and dropped if
+// it lies at r_cut or more from the block's box.  Survivors are compacted
+// with a ballot into a 128-entry LDS ring; every 64 survivors are swept by
+// all lanes with broadcast LDS reads.
 template <bool NEWTON>
 __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
                                                     const float* __restrict__ mass_s, int64_t n,
                                                     double L, double cell, double inv_rcut,
-                                                    PolyF32 P, float* __restrict__ partial) {
+                                                    PolyF32 P, float* __restrict__ partial,
+                                                    unsigned long long* __restrict__ counters) {
     const int64_t item = xcd_item(blockIdx.x, ia.per_xcd);
     if (item >= ia.nitem) return;
     const int lane = threadIdx.x;
@@ -69,71 +134,105 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
+    const int32_t nt = ia.bcount[b];
     const IBox B = ia.bbox[b];
     const double ox = 0.5 * (double)(B.lo[0] + B.hi[0]) * cell;
     const double oy = 0.5 * (double)(B.lo[1] + B.hi[1]) * cell;
     const double oz = 0.5 * (double)(B.lo[2] + B.hi[2]) * cell;
-    const int64_t t = (int64_t)b * kBlock + lane;
+    // half sides of the block box in units of r_cut, widened slightly so the
+    // pruning test can only keep too much
+    const float hx = (float)(0.5 * (double)(B.hi[0] - B.lo[0]) * cell * inv_rcut) * 1.0001f + 1e-6f;
+    const float hy = (float)(0.5 * (double)(B.hi[1] - B.lo[1]) * cell * inv_rcut) * 1.0001f + 1e-6f;
+    const float hz = (float)(0.5 * (double)(B.hi[2] - B.lo[2]) * cell * inv_rcut) * 1.0001f + 1e-6f;
+    const float keep2 = 1.0002f;
+    const int64_t t = (int64_t)ia.bstart[b] + lane;
     float xi = 0.f, yi = 0.f, zi = 0.f;
-    if (t < n) {
+    if (lane < nt) {
         xi = (float)((pos_s[t] - ox) * inv_rcut);
         yi = (float)((pos_s[n + t] - oy) * inv_rcut);
         zi = (float)((pos_s[2 * n + t] - oz) * inv_rcut);
     }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
-    __shared__ float4 tile[kBlock];
+    __shared__ float4 tile[2 * kBlock];
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-    for (int32_t base = s0; base < s1; base += kBlock) {
+    int count = 0;                                   // staged sources (wave-uniform)
+    int64_t staged = 0;
+    int64_t rcur = s1 > s0 ? find_range(ia.rpre, r_lo, r_hi, s0) : r_lo;
+
+    double px = 0, py = 0, pz = 0;
+    float pm = 0.f;
+    int pc = 13;
+    bool pv = false;
+    auto fetch = [&](int32_t base) {
         const int32_t p = base + lane;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (p < s1) {
-            const int64_t r = find_range(ia.rpre, r_lo, r_hi, p);
+        pv = p < s1;
+        int64_t r = rcur;
+        const int32_t end_cur = rcur < r_hi ? ia.rpre[rcur + 1] : S;
+        if (base + kBlock > end_cur) {
+            const int64_t top = rcur + kBlock < r_hi ? rcur + kBlock : r_hi;
+            if (pv) r = find_range(ia.rpre, rcur, top, p);
+        }
+        if (pv) {
             const int64_t j = (int64_t)ia.rbeg[r] + (p - ia.rpre[r]);
-            const int c = ia.rcode[r];
-            const double sx = (double)(c / 9 - 1) * L;
-            const double sy = (double)((c / 3) % 3 - 1) * L;
-            const double sz = (double)(c % 3 - 1) * L;
-            v.x = (float)((pos_s[j] + sx - ox) * inv_rcut);
-            v.y = (float)((pos_s[n + j] + sy - oy) * inv_rcut);
-            v.z = (float)((pos_s[2 * n + j] + sz - oz) * inv_rcut);
-            v.w = mass_s[j];
+            pc = ia.rcode[r];
+            px = pos_s[j];
+            py = pos_s[n + j];
+            pz = pos_s[2 * n + j];
+            pm = mass_s[j];
         }
-        __syncthreads();
-        tile[lane] = v;
-        __syncthreads();
-        float tx = 0.f, ty = 0.f, tz = 0.f;
+        rcur = readlane64(r, kBlock - 1);
+    };
+    if (s0 < s1) fetch(s0);
+    for (int32_t base = s0; base < s1; base += kBlock) {
+        bool keep = false;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (pv) {
+            const double sx = (double)(pc / 9 - 1) * L;
+            const double sy = (double)((pc / 3) % 3 - 1) * L;
+            const double sz = (double)(pc % 3 - 1) * L;
+            v.x = (float)((px + sx - ox) * inv_rcut);
+            v.y = (float)((py + sy - oy) * inv_rcut);
+            v.z = (float)((pz + sz - oz) * inv_rcut);
+            v.w = pm;
+            const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
+            const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
+            const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
+            keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+        }
+        const uint64_t bal = __ballot(keep);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (keep) tile[count + rank] = v;
+        const int got = __popcll(bal);
+        count += got;
+        staged += got;
+        // the next window's loads stay in flight while this tile is swept
+        if (base + kBlock < s1) fetch(base + kBlock);
+        if (count >= kBlock) {
+            wave_sync();
+            float tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll 8
-        for (int q = 0; q < kBlock; ++q) {
-            const float4 sj = tile[q];
-            const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
-            float r2 = fmaf(dx, dx, P.eps2n);
-            r2 = fmaf(dy, dy, r2);
-            r2 = fmaf(dz, dz, r2);
-            float y = __builtin_amdgcn_rsqf(r2);
-            if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
-            const float u = fmaf(r2, P.tscale, -1.f);
-            float h = P.c[9];
-            h = fmaf(h, u, P.c[8]);
-            h = fmaf(h, u, P.c[7]);
-            h = fmaf(h, u, P.c[6]);
-            h = fmaf(h, u, P.c[5]);
-            h = fmaf(h, u, P.c[4]);
-            h = fmaf(h, u, P.c[3]);
-            h = fmaf(h, u, P.c[2]);
-            h = fmaf(h, u, P.c[1]);
-            h = fmaf(h, u, P.c[0]);
-            const float y3 = y * y * y;
-            float F = (y3 - h) * sj.w;
-            F = r2 < P.cut2 ? F : 0.f;
-            tx = fmaf(F, dx, tx);
-            ty = fmaf(F, dy, ty);
-            tz = fmaf(F, dz, tz);
+            for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+            kahan_add(ax, cx, tx);
+            kahan_add(ay, cy, ty);
+            kahan_add(az, cz, tz);
+            wave_sync();
+            count -= kBlock;
+            if (lane < count) tile[lane] = tile[kBlock + lane];
+            wave_sync();
         }
-        // Kahan: true sum ~ a - c
-        float yk, tk;
-        yk = tx - cx; tk = ax + yk; cx = (tk - ax) - yk; ax = tk;
-        yk = ty - cy; tk = ay + yk; cy = (tk - ay) - yk; ay = tk;
-        yk = tz - cz; tk = az + yk; cz = (tk - az) - yk; az = tk;
+    }
+    if (count > 0) {
+        wave_sync();
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+        kahan_add(ax, cx, tx);
+        kahan_add(ay, cy, ty);
+        kahan_add(az, cz, tz);
+    }
+    if (counters && lane == 0) {
+        atomicAdd(counters, (unsigned long long)staged * (unsigned long long)nt);
+        atomicAdd(counters + 1, (unsigned long long)staged * (unsigned long long)kBlock);
     }
     float* o = partial + item * 6 * kBlock;
     o[0 * kBlock + lane] = ax;
@@ -144,15 +243,20 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
     o[5 * kBlock + lane] = cz;
 }
 
+// One thread per (block, lane): sum the item partials of the block in
+// order (FP64), scale, and scatter to input order.
 __global__ void __launch_bounds__(256) reduce_f32_kernel(const int64_t* __restrict__ ioff,
+                                                         const int32_t* __restrict__ bstart,
+                                                         const int32_t* __restrict__ bcount,
+                                                         int64_t nblock,
                                                          const float* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
                                                          int64_t n, double scale,
                                                          float* __restrict__ acc) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int64_t b = t / kBlock;
-    const int l = (int)(t % kBlock);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = g / kBlock;
+    const int l = (int)(g % kBlock);
+    if (b >= nblock || l >= bcount[b]) return;
     double sx = 0, sy = 0, sz = 0;
     for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) {
         const float* o = partial + it * 6 * kBlock;
@@ -160,7 +264,7 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(const int64_t* __restri
         sy += (double)o[1 * kBlock + l] - (double)o[4 * kBlock + l];
         sz += (double)o[2 * kBlock + l] - (double)o[5 * kBlock + l];
     }
-    const int64_t i = perm[t];
+    const int64_t i = perm[(int64_t)bstart[b] + l];
     acc[i] = (float)(sx * scale);
     acc[n + i] = (float)(sy * scale);
     acc[2 * n + i] = (float)(sz * scale);
@@ -186,9 +290,10 @@ __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* _
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
-    const int64_t t = (int64_t)b * kBlock + lane;
+    const bool active = lane < ia.bcount[b];
+    const int64_t t = active ? (int64_t)ia.bstart[b] + lane : -2;
     double xi = 0, yi = 0, zi = 0;
-    if (t < n) {
+    if (active) {
         xi = pos_s[t];
         yi = pos_s[n + t];
         zi = pos_s[2 * n + t];
@@ -255,13 +360,16 @@ __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* _
 #pragma clang fp contract(on)
 
 __global__ void __launch_bounds__(256) reduce_f64_kernel(const int64_t* __restrict__ ioff,
+                                                         const int32_t* __restrict__ bstart,
+                                                         const int32_t* __restrict__ bcount,
+                                                         int64_t nblock,
                                                          const double* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
                                                          int64_t n, double* __restrict__ acc) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int64_t b = t / kBlock;
-    const int l = (int)(t % kBlock);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = g / kBlock;
+    const int l = (int)(g % kBlock);
+    if (b >= nblock || l >= bcount[b]) return;
     double sx = 0, sy = 0, sz = 0;
     for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) {
         const double* o = partial + it * 3 * kBlock;
@@ -269,24 +377,27 @@ __global__ void __launch_bounds__(256) reduce_f64_kernel(const int64_t* __restri
         sy += o[1 * kBlock + l];
         sz += o[2 * kBlock + l];
     }
-    const int64_t i = perm[t];
+    const int64_t i = perm[(int64_t)bstart[b] + l];
     acc[i] = sx;
     acc[n + i] = sy;
     acc[2 * n + i] = sz;
 }
 
 __global__ void __launch_bounds__(256) reduce_count_kernel(const int64_t* __restrict__ ioff,
+                                                           const int32_t* __restrict__ bstart,
+                                                           const int32_t* __restrict__ bcount,
+                                                           int64_t nblock,
                                                            const int32_t* __restrict__ pc,
                                                            const int32_t* __restrict__ perm,
                                                            int64_t n, int64_t* __restrict__ counts,
                                                            unsigned long long* __restrict__ total) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int64_t b = t / kBlock;
-    const int l = (int)(t % kBlock);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = g / kBlock;
+    const int l = (int)(g % kBlock);
+    if (b >= nblock || l >= bcount[b]) return;
     int64_t s = 0;
     for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) s += pc[it * kBlock + l];
-    if (counts) counts[perm[t]] = s;
+    if (counts) counts[perm[(int64_t)bstart[b] + l]] = s;
     atomicAdd(total, (unsigned long long)s);
 }
 
@@ -296,6 +407,8 @@ ItemArgs item_args(const BlockLists& bl, int chunk) {
     ia.is0 = bl.is0.as<int32_t>();
     ia.nitem = bl.nitem;
     ia.per_xcd = (bl.nitem + 7) / 8;
+    ia.bstart = bl.bstart.as<int32_t>();
+    ia.bcount = bl.bcount.as<int32_t>();
     ia.bbox = bl.box.as<IBox>();
     ia.roff = bl.roff.as<int64_t>();
     ia.rbeg = bl.rbeg.as<int32_t>();
@@ -323,12 +436,12 @@ int make_poly(const pp_box_params& p, PolyF32* out) {
 
 int launch_pp_f32(const BlockLists& bl, const double* pos_s, const float* mass_s, int64_t n,
                   const pp_box_params& p, const PolyF32& poly, int chunk, float* partial,
-                  hipStream_t s) {
+                  unsigned long long* counters, hipStream_t s) {
     if (bl.nitem == 0) return PP_OK;
     ItemArgs ia = item_args(bl, chunk);
     const double cell = p.L / (double)(1ll << p.key_bits);
     hipLaunchKernelGGL(pp_f32_kernel<false>, dim3((unsigned)(ia.per_xcd * 8)), dim3(kBlock), 0, s,
-                       ia, pos_s, mass_s, n, p.L, cell, 1.0 / p.rcut, poly, partial);
+                       ia, pos_s, mass_s, n, p.L, cell, 1.0 / p.rcut, poly, partial, counters);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
@@ -336,8 +449,9 @@ int launch_pp_f32(const BlockLists& bl, const double* pos_s, const float* mass_s
 int launch_reduce_f32(const BlockLists& bl, const float* partial, const int32_t* perm, int64_t n,
                       double scale, float* acc, hipStream_t s) {
     if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       bl.ioff.as<int64_t>(), partial, perm, n, scale, acc);
+    hipLaunchKernelGGL(reduce_f32_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
+                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
+                       bl.nblock, partial, perm, n, scale, acc);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
@@ -356,8 +470,9 @@ int launch_pp_f64(const BlockLists& bl, const double* pos_s, const double* mass_
 int launch_reduce_f64(const BlockLists& bl, const double* partial, const int32_t* perm, int64_t n,
                       double* acc, hipStream_t s) {
     if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       bl.ioff.as<int64_t>(), partial, perm, n, acc);
+    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
+                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
+                       bl.nblock, partial, perm, n, acc);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
@@ -376,8 +491,9 @@ int launch_count(const BlockLists& bl, const double* pos_s, int64_t n, const pp_
 int launch_reduce_count(const BlockLists& bl, const int32_t* partial, const int32_t* perm,
                         int64_t n, int64_t* counts, unsigned long long* total, hipStream_t s) {
     if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       bl.ioff.as<int64_t>(), partial, perm, n, counts, total);
+    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
+                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
+                       bl.nblock, partial, perm, n, counts, total);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
