@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-box batched-vs-per-box comparison")
     return ap.parse_args()
 
 
@@ -84,6 +86,72 @@ def cpu_baseline(box, acc_gpu, budget_s):
             "max": float(e.max()) if e.size else 0.0,
             "zero_neighbour_exact": bool(np.all(a[:, ~has] == 0))}
     return base, errs
+
+
+def bench_batched(steps, warmup):
+    """64 independent boxes (N uniform in 16^3..96^3, L in 50-300 Mpc/h,
+    clustered fraction 0-0.8): one batched pp_batch_accel per step (all
+    stages over all boxes, one persistent work-stealing PP launch replayed
+    from a hipGraph) against 64 separate pp_accel calls per step."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1802_09824_amd as pp
+
+    boxes = workloads.make_batch()
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes], axis=1), device="cuda")
+    mass = torch.tensor(np.concatenate([b.mass for b in boxes]), device="cuda")
+    N = pos.shape[1]
+    acc = torch.empty((3, N), dtype=torch.float32, device="cuda")
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    bp.accel(pos, mass, out=acc)
+    interactions = bp.count_interactions()
+    for _ in range(warmup):
+        bp.accel(pos, mass, out=acc)
+    bp.set_timing(True)
+    graph_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bp.accel(pos, mass, out=acc)
+        graph_ms.append(bp.stats()["pp_kernel_ms"])
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / steps
+    acc_batched = acc.cpu().numpy()
+
+    # per box: separate inputs, plans and launches
+    per = []
+    for b in boxes:
+        pb = torch.tensor(b.pos, device="cuda")
+        mb = torch.tensor(b.mass, device="cuda")
+        ab = torch.empty((3, b.n), dtype=torch.float32, device="cuda")
+        per.append((pp.Plan(b.params, b.n), pb, mb, ab))
+    for plan, pb, mb, ab in per:
+        plan.accel(pb, mb, out=ab)
+        plan.set_timing(True)
+    kernel_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for plan, pb, mb, ab in per:
+            plan.accel(pb, mb, out=ab)
+            kernel_ms += plan.stats()["pp_kernel_ms"]
+    torch.cuda.synchronize()
+    t_per = (time.perf_counter() - t0) / steps
+    same = all(np.array_equal(ab.cpu().numpy(), acc_batched[:, o:o + b.n])
+               for (plan, pb, mb, ab), b, o in zip(per, boxes, np.cumsum([0] + [x.n for x in boxes])))
+    return {
+        "workload": "batch-64-boxes-N16^3..96^3-L50-300",
+        "boxes": len(boxes), "particles": int(N), "interactions_per_step": interactions,
+        "batched": {"ms_per_step": 1e3 * t_batched, "value": interactions / t_batched,
+                    "pp_graph_ms": float(np.mean(graph_ms))},
+        "per_box": {"ms_per_step": 1e3 * t_per, "value": interactions / t_per,
+                    "pp_kernel_ms_sum": kernel_ms / steps},
+        "speedup_whole_step": t_per / t_batched,
+        "speedup_pp": (kernel_ms / steps) / float(np.mean(graph_ms)),
+        "bit_identical_to_per_box": bool(same),
+        "unit": "interactions/s",
+    }
 
 
 def main():
@@ -145,6 +213,10 @@ def main():
         base, errs = cpu_baseline(box, acc.cpu().numpy(), args.cpu_seconds)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = errs
+    if not args.no_batched:
+        del plan, pos, mass, acc
+        torch.cuda.empty_cache()
+        out["batched_vs_per_box"] = bench_batched(max(1, min(args.steps, 5)), 1)
     print(json.dumps(out), flush=True)
 
 

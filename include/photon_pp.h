@@ -128,7 +128,7 @@ void pp_leaves_free(pp_leaves* lv);
  * leaves in key order; within a row entries ascend by (B, code) with
  * code = 9 (s_x + 1) + 3 (s_y + 1) + (s_z + 1).
  * Synchronises the stream (reads the entry count back).                    */
-int pp_near_pairs(const pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* stream);
+int pp_near_pairs(pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* stream);
 int pp_pairs_count(const pp_pairs* pr, int64_t* nrows, int64_t* nentries);
 /* Copy the canonical CSR out: row_ptr [nrows + 1] int64, src_leaf
  * [nentries] int32, shift_code [nentries] uint8.  Synchronous.             */
@@ -172,14 +172,72 @@ typedef struct pp_stats {
 /* Waits for the last PP kernel when timing is on.                          */
 int pp_plan_stats(pp_plan* plan, pp_stats* out);
 
-/* Turn HIP-event timing of the PP kernel on (1) or off (0).                */
+/* Turn HIP-event timing of the PP kernel on (1) or off (0).  With graph
+ * replay the events bracket the whole replayed graph.                      */
 int pp_plan_set_timing(pp_plan* plan, int on);
+
+/* Launch shape of the FP32 PP kernel.
+ *  chunk        source-list positions per work item (multiple of 64)
+ *  persistent   0: one workgroup per work item; 1: a fixed grid of
+ *               waves_per_cu waves per CU pulling items from per-XCD queues
+ *               with stealing
+ *  waves_per_cu used by the persistent form, 1..64
+ *  use_graph    1: capture the persistent kernel and the reduction in a
+ *               hipGraph once and replay it (needs persistent = 1)
+ *  variant      arithmetic ablations for precision studies (bit flags):
+ *               1 = one Newton step after the hardware rsqrt, 2 = no Kahan
+ *               compensation of the per-target sums, 4 = offsets from the
+ *               box origin instead of the FP64 block centre.  0 is the
+ *               production kernel.
+ * The chunk grows by itself when the lists are long enough that more than
+ * 2^21 work items would be needed.
+ * Defaults: plans {4096, 0, 16, 0, 0}; batch plans {4096, 1, 16, 1, 0}.    */
+typedef struct pp_tuning {
+    int32_t chunk, persistent, waves_per_cu, use_graph, variant;
+} pp_tuning;
+int pp_plan_get_tuning(const pp_plan* plan, pp_tuning* t);
+int pp_plan_set_tuning(pp_plan* plan, const pp_tuning* t);
+
+/* Autotuner: times the PP stage (HIP events, median of 3 after a warm run)
+ * for every chunk in {1024, 2048, 4096, 8192} and launch shape in {one
+ * workgroup per item, persistent with 8, 16 or 32 waves per CU} on the
+ * given particles, and keeps the fastest in the plan.  With cache_path
+ * (may be NULL) the choice is looked up first and stored afterwards, one
+ * line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent waves graph" per shape
+ * class.  The caller's inputs are not modified.  Synchronises the stream.  */
+int pp_autotune(pp_plan* plan, const double* pos, const float* mass, int64_t n,
+                const char* cache_path, void* stream);
 
 /* Count, per target, the pairs with s < rcut and j != i (FP64 test), using
  * the plan's lists from the last pp_accel call on the same positions.
  *   counts device [n] int64 (out, input order; may be NULL) ; total (host).
  * Synchronises the stream.                                                 */
 int pp_count_interactions(pp_plan* plan, int64_t* counts, int64_t* total, void* stream);
+
+/* ------------------------------------------------------------- batches --
+ * Many independent periodic boxes of different N, L and split parameters in
+ * one pass (the task-queue idea of sec. 4.3 taken to whole boxes): every
+ * stage runs once over all boxes, and the PP kernel is one persistent,
+ * work-stealing launch over the work items of all boxes, captured in a
+ * hipGraph and replayed.  Boxes must share key_bits and leaf_max.
+ *   params [nbox], n [nbox]: box x owns particles [off_x, off_x + n[x]) of
+ *   the concatenated arrays, off_x = n[0] + ... + n[x-1].
+ *   pos device SoA [3][N] float64 (N = sum n), mass [N] float32,
+ *   acc SoA [3][N] float32 (out), all in the concatenated input order.
+ * pp_batch_accel synchronises the stream (list sizes).                     */
+int pp_batch_plan_create(int nbox, const pp_box_params* params, const int64_t* n,
+                         pp_batch_plan** out);
+void pp_batch_plan_destroy(pp_batch_plan* bp);
+int pp_batch_accel(pp_batch_plan* bp, const double* pos, const float* mass, float* acc,
+                   void* stream);
+int pp_batch_count_interactions(pp_batch_plan* bp, int64_t* counts, int64_t* total, void* stream);
+int pp_batch_stats(pp_batch_plan* bp, pp_stats* out);
+int pp_batch_set_timing(pp_batch_plan* bp, int on);
+int pp_batch_get_tuning(const pp_batch_plan* bp, pp_tuning* t);
+int pp_batch_set_tuning(pp_batch_plan* bp, const pp_tuning* t);
+/* Autotuner for a batch (same sweep; the persistent shapes use graph replay). */
+int pp_batch_autotune(pp_batch_plan* bp, const double* pos, const float* mass,
+                      const char* cache_path, void* stream);
 
 #ifdef __cplusplus
 }

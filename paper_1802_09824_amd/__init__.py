@@ -36,6 +36,14 @@ class pp_box_params(C.Structure):
                 ("G", C.c_double), ("leaf_max", C.c_int32), ("key_bits", C.c_int32)]
 
 
+class pp_tuning(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("use_graph", C.c_int32), ("variant", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class pp_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("nleaf", C.c_int64), ("nblock", C.c_int64),
                 ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
@@ -65,6 +73,18 @@ _SIGS = {
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
     "pp_plan_set_timing": (_i32, [_P, _i32]),
+    "pp_plan_get_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
+    "pp_plan_set_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
+    "pp_batch_plan_create": (_i32, [_i32, _P, _P, C.POINTER(_P)]),
+    "pp_batch_plan_destroy": (None, [_P]),
+    "pp_batch_accel": (_i32, [_P, _P, _P, _P, _P]),
+    "pp_batch_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
+    "pp_batch_stats": (_i32, [_P, C.POINTER(pp_stats)]),
+    "pp_batch_set_timing": (_i32, [_P, _i32]),
+    "pp_batch_get_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
+    "pp_batch_set_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
+    "pp_autotune": (_i32, [_P, _P, _P, _i64, C.c_char_p, _P]),
+    "pp_batch_autotune": (_i32, [_P, _P, _P, C.c_char_p, _P]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -234,6 +254,24 @@ class Plan:
     def set_timing(self, on: bool = True):
         _check(_lib.pp_plan_set_timing(self._h, 1 if on else 0), "pp_plan_set_timing")
 
+    def get_tuning(self) -> dict:
+        t = pp_tuning()
+        _check(_lib.pp_plan_get_tuning(self._h, C.byref(t)), "pp_plan_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = pp_tuning(**{**self.get_tuning(), **kw})
+        _check(_lib.pp_plan_set_tuning(self._h, C.byref(t)), "pp_plan_set_tuning")
+
+    def autotune(self, pos: torch.Tensor, mass: torch.Tensor, cache_path: str | None = None,
+                 stream=None) -> dict:
+        n = pos.shape[1]
+        _check(_lib.pp_autotune(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                _dev(mass, torch.float32, (n,), "mass"), n,
+                                cache_path.encode() if cache_path else None, _stream(stream)),
+               "pp_autotune")
+        return self.get_tuning()
+
     def count_interactions(self, per_target: bool = False, stream=None):
         tot = _i64(0)
         counts = None
@@ -249,3 +287,76 @@ class Plan:
 
 def pp_plan_create(params, n_max: int) -> Plan:
     return Plan(params, n_max)
+
+
+class BatchPlan:
+    """pp_batch_plan: many independent boxes, one persistent launch."""
+
+    def __init__(self, params_list, ns):
+        import numpy as np
+        self.nbox = len(params_list)
+        arr = (pp_box_params * self.nbox)(*[make_params(p) for p in params_list])
+        self._keep = arr
+        self.ns = np.ascontiguousarray(ns, dtype=np.int64)
+        self.N = int(self.ns.sum())
+        h = _P(None)
+        _check(_lib.pp_batch_plan_create(self.nbox, C.cast(arr, _P), self.ns.ctypes.data_as(_P),
+                                         C.byref(h)), "pp_batch_plan_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.pp_batch_plan_destroy(self._h)
+            self._h = C.c_void_p(None)
+
+    def accel(self, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        n = self.N
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+        _check(_lib.pp_batch_accel(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                   _dev(mass, torch.float32, (n,), "mass"),
+                                   _dev(out, torch.float32, (3, n), "acc"), _stream(stream)),
+               "pp_batch_accel")
+        return out
+
+    def count_interactions(self, per_target: bool = False, stream=None):
+        tot = _i64(0)
+        counts = None
+        ptr = C.c_void_p(None)
+        if per_target:
+            counts = torch.zeros(self.N, dtype=torch.int64, device="cuda")
+            ptr = C.c_void_p(counts.data_ptr())
+        _check(_lib.pp_batch_count_interactions(self._h, ptr, C.byref(tot), _stream(stream)),
+               "pp_batch_count_interactions")
+        return (int(tot.value), counts) if per_target else int(tot.value)
+
+    def stats(self) -> dict:
+        st = pp_stats()
+        _check(_lib.pp_batch_stats(self._h, C.byref(st)), "pp_batch_stats")
+        return {k: getattr(st, k) for k, _ in pp_stats._fields_}
+
+    def set_timing(self, on: bool = True):
+        _check(_lib.pp_batch_set_timing(self._h, 1 if on else 0), "pp_batch_set_timing")
+
+    def get_tuning(self) -> dict:
+        t = pp_tuning()
+        _check(_lib.pp_batch_get_tuning(self._h, C.byref(t)), "pp_batch_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = pp_tuning(**{**self.get_tuning(), **kw})
+        _check(_lib.pp_batch_set_tuning(self._h, C.byref(t)), "pp_batch_set_tuning")
+
+    def autotune(self, pos: torch.Tensor, mass: torch.Tensor, cache_path: str | None = None,
+                 stream=None) -> dict:
+        n = self.N
+        _check(_lib.pp_batch_autotune(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                      _dev(mass, torch.float32, (n,), "mass"),
+                                      cache_path.encode() if cache_path else None, _stream(stream)),
+               "pp_batch_autotune")
+        return self.get_tuning()
+
+
+def pp_batch_plan_create(params_list, ns) -> BatchPlan:
+    return BatchPlan(params_list, ns)

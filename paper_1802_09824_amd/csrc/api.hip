@@ -1,9 +1,14 @@
-// C ABI of the library (include/photon_pp.h): argument checks, plans and
-// the order of the path's stages.  All compute runs in the HIP kernels of
-// keys_sort.hip, tree.hip and pp_kernels.hip.
+// C ABI of the library (include/photon_pp.h): argument checks, plans, the
+// order of the path's stages, the batched persistent launch and its graph,
+// and the autotuner.  All compute runs in the HIP kernels of keys_sort.hip,
+// tree.hip and pp_kernels.hip.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 
 #include "pp_internal.h"
@@ -12,6 +17,7 @@
 namespace pp {
 
 static thread_local std::string g_last_error;
+static uint64_t g_alloc_generation = 1;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -27,10 +33,12 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
     return e == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE;
 }
 
+uint64_t alloc_generation() { return g_alloc_generation; }
+
 int DevBuf::reserve(size_t need) {
     if (need <= bytes) return PP_OK;
     release();
-    size_t want = need + need / 4 + 256;
+    const size_t want = need + need / 4 + 256;
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
         p = nullptr;
@@ -41,6 +49,7 @@ int DevBuf::reserve(size_t need) {
         return e == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE;
     }
     bytes = want;
+    ++g_alloc_generation;
     return PP_OK;
 }
 
@@ -50,15 +59,25 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-Geo make_geo(const pp_box_params& p) {
-    Geo g;
-    g.L = p.L;
-    g.bits = p.key_bits;
-    g.W = (int64_t)1 << p.key_bits;
+BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
+    BoxDev b{};
+    b.L = p.L;
+    b.qscale = ldexp(1.0, p.key_bits) / p.L;
+    b.cell = p.L / ldexp(1.0, p.key_bits);
+    b.inv_rcut = 1.0 / p.rcut;
+    b.scale = p.G / (p.rcut * p.rcut);
+    b.rs = p.rs;
+    b.rcut = p.rcut;
+    b.eps = p.eps;
+    b.G = p.G;
+    b.W = (int64_t)1 << p.key_bits;
     const double r = p.rcut * ldexp(1.0, p.key_bits) / p.L;
-    g.T = (int64_t)ceil(r * r);
-    g.qscale = ldexp(1.0, p.key_bits) / p.L;
-    return g;
+    b.T = (int64_t)ceil(r * r);
+    b.emax = (int64_t)floor(2.0 * p.rcut * (double)b.W / p.L);
+    b.poff = poff;
+    b.n = n;
+    make_poly(p, &b.poly);
+    return b;
 }
 
 int validate_params(const pp_box_params* p, bool need_poly) {
@@ -81,48 +100,339 @@ int validate_params(const pp_box_params* p, bool need_poly) {
     return PP_OK;
 }
 
+// ------------------------------------------------------------------ batch --
+struct Batch {
+    int nbox = 0;
+    int64_t n_max = 0;                    // capacity (particles)
+    std::vector<pp_box_params> params;
+    std::vector<int64_t> poff;            // host [nbox + 1]
+    int64_t N = 0;
+    DevBuf box_dev, poff_dev;
+    BatchDev bd{};
+    Work w;
+    pp_tuning tune{4096, 0, 16, 0, 0};
+    int graph_variant = -1;
+    pp_stats st{};
+    bool lists_valid = false, evaluated_valid = false;
+    bool timing = false, timed = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf partial, pcount, counters, queues;
+    // captured PP graph (persistent kernel + reduction)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;     // capture only (the null stream cannot be captured)
+    uint64_t graph_gen = 0;
+    const void* graph_acc = nullptr;
+
+    ~Batch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+
+    int init(int nb, const pp_box_params* p, const int64_t* n, bool need_poly = true) {
+        if (nb < 1) return fail(PP_EINVAL, "need at least one box");
+        for (int x = 0; x < nb; ++x) {
+            PP_TRY(validate_params(&p[x], need_poly));
+            if (n[x] < 0) return fail(PP_EINVAL, "negative particle count");
+            if (p[x].key_bits != p[0].key_bits || p[x].leaf_max != p[0].leaf_max)
+                return fail(PP_EINVAL, "all boxes of a batch must share key_bits and leaf_max");
+        }
+        int dev_count = 0;
+        hipError_t e = hipGetDeviceCount(&dev_count);
+        if (e != hipSuccess || dev_count == 0) {
+            (void)hipGetLastError();
+            return fail(PP_EDEVICE, "no HIP device available");
+        }
+        nbox = nb;
+        params.assign(p, p + nb);
+        poff.assign(nb + 1, 0);
+        for (int x = 0; x < nb; ++x) poff[x + 1] = poff[x] + n[x];
+        N = poff[nb];
+        n_max = N;
+        if (N > INT32_MAX - 4096) return fail(PP_EINVAL, "too many particles (int32 indices)");
+        std::vector<BoxDev> hb(nb);
+        for (int x = 0; x < nb; ++x) hb[x] = make_boxdev(p[x], poff[x], n[x]);
+        PP_TRY(box_dev.reserve(sizeof(BoxDev) * nb));
+        PP_TRY(poff_dev.reserve(sizeof(int64_t) * (nb + 1)));
+        PP_HIP(hipMemcpy(box_dev.p, hb.data(), sizeof(BoxDev) * nb, hipMemcpyHostToDevice));
+        PP_HIP(hipMemcpy(poff_dev.p, poff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
+        bd.box = box_dev.as<BoxDev>();
+        bd.poff = poff_dev.as<int64_t>();
+        bd.nbox = nb;
+        bd.bits = p[0].key_bits;
+        bd.leaf_max = p[0].leaf_max;
+        const int64_t m = N > 0 ? N : 1;
+        PP_TRY(w.keys.reserve(8 * m));
+        PP_TRY(w.keys_s.reserve(8 * m));
+        PP_TRY(w.iota.reserve(4 * m));
+        PP_TRY(w.perm.reserve(4 * m));
+        PP_TRY(w.pos_s.reserve(24 * m));
+        PP_TRY(w.mass_s.reserve(4 * m));
+        PP_TRY(w.bad.reserve(64));
+        PP_TRY(counters.reserve(64));
+        PP_TRY(queues.reserve(64));
+        return PP_OK;
+    }
+
+    // Stages shared by every entry point: keys, sort, gather, leaves, trees,
+    // block lists.  Synchronises the stream.
+    int prepare(const double* pos, const float* mass_f, const double* mass_d, hipStream_t s) {
+        lists_valid = false;
+        evaluated_valid = false;
+        w.pos_n = N;
+        PP_HIP(hipMemsetAsync(w.bad.p, 0, sizeof(int), s));
+        PP_TRY(stage_keys(bd, N, pos, w, s));
+        PP_TRY(stage_sort(bd, N, w, s));
+        if (mass_d) PP_TRY(w.mass_sd.reserve(8 * (N > 0 ? N : 1)));
+        PP_TRY(stage_gather(bd, N, pos, mass_f, mass_d, w, s));
+        PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s));
+        int bad = 0;
+        PP_HIP(hipMemcpyAsync(&bad, w.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        PP_HIP(hipStreamSynchronize(s));
+        if (bad) return fail(PP_EINVAL, "non-finite position or mass");
+        PP_TRY(stage_trees(bd, w, s));
+        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s));
+        st.n = N;
+        st.nleaf = w.nleaf;
+        st.nblock = w.nblock;
+        st.nrange = w.nrange;
+        st.nitem = w.nitem;
+        st.candidates = w.candidates;
+        st.interactions = -1;
+        st.evaluated = -1;
+        st.lane_pairs = -1;
+        st.pp_kernel_ms = -1.0;
+        lists_valid = true;
+        return PP_OK;
+    }
+
+    int run_pp_direct(float* acc, hipStream_t s) {
+        unsigned long long* ctr = counters.as<unsigned long long>();
+        PP_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), s));
+        if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
+        if (timing) PP_HIP(hipEventRecord(ev0, s));
+        PP_TRY(launch_pp_f32(bd, w, tune.chunk, tune.persistent ? Mode::kPersistent : Mode::kGrid,
+                             tune.waves_per_cu, tune.variant, partial.as<float>(), ctr,
+                             queues.as<unsigned>(), s));
+        if (timing) {
+            PP_HIP(hipEventRecord(ev1, s));
+            timed = true;
+        }
+        PP_TRY(launch_reduce_f32(bd, w, partial.as<float>(), acc, s));
+        evaluated_valid = true;
+        return PP_OK;
+    }
+
+    // Records reset + persistent kernel + reduction on a private stream; the
+    // graph is then launched on the caller's stream.  Nothing runs here.
+    int capture(float* acc) {
+        if (!cap_stream) PP_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        hipStream_t s = cap_stream;
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        if (graph) {
+            (void)hipGraphDestroy(graph);
+            graph = nullptr;
+        }
+        PP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = launch_reset_queues(queues.as<unsigned>(), s);
+        if (rc == PP_OK)
+            rc = launch_pp_f32(bd, w, tune.chunk, Mode::kPersistent, tune.waves_per_cu, tune.variant,
+                               partial.as<float>(), nullptr, queues.as<unsigned>(), s);
+        if (rc == PP_OK) rc = launch_reduce_f32(bd, w, partial.as<float>(), acc, s);
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc != PP_OK) return rc;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        PP_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        graph_gen = alloc_generation();
+        graph_acc = acc;
+        graph_variant = tune.variant;
+        return PP_OK;
+    }
+
+    int run_f32(float* acc, hipStream_t s) {
+        PP_TRY(partial.reserve(sizeof(float) * 6 * kBlock * (w.nitem + 1)));
+        if (tune.persistent && tune.use_graph) {
+            if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
+                graph_variant != tune.variant)
+                PP_TRY(capture(acc));
+            if (timing) PP_HIP(hipEventRecord(ev0, s));
+            PP_HIP(hipGraphLaunch(gexec, s));
+            if (timing) {
+                PP_HIP(hipEventRecord(ev1, s));
+                timed = true;
+            }
+            evaluated_valid = false;
+            return PP_OK;
+        }
+        return run_pp_direct(acc, s);
+    }
+
+    int stats(pp_stats* out) {
+        st.pp_kernel_ms = -1.0;
+        if (timing && timed) {
+            PP_HIP(hipEventSynchronize(ev1));
+            float ms = 0.f;
+            PP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            st.pp_kernel_ms = ms;
+        }
+        st.evaluated = st.lane_pairs = -1;
+        if (evaluated_valid) {
+            unsigned long long h[2] = {0, 0};
+            PP_HIP(hipMemcpy(h, counters.p, sizeof(h), hipMemcpyDeviceToHost));
+            st.evaluated = (int64_t)h[0];
+            st.lane_pairs = (int64_t)h[1];
+        }
+        *out = st;
+        return PP_OK;
+    }
+
+    // Time the PP stage (events around kernel or graph) for the current
+    // tuning: median of `reps` runs after one warm run.
+    int time_pp(const double* pos, const float* mass, float* acc, int reps, hipStream_t s,
+                float* ms_out) {
+        const bool was = timing;
+        PP_TRY(set_timing(1));
+        PP_TRY(prepare(pos, mass, nullptr, s));
+        PP_TRY(run_f32(acc, s));
+        std::vector<float> t;
+        for (int r = 0; r < reps; ++r) {
+            PP_TRY(run_f32(acc, s));
+            PP_HIP(hipEventSynchronize(ev1));
+            float ms = 0.f;
+            PP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        *ms_out = t[t.size() / 2];
+        timing = was;
+        return PP_OK;
+    }
+
+    std::string shape_key() const {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        std::string arch = "gpu";
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+        int lg = 0;
+        while ((int64_t(1) << (lg + 1)) <= (N > 0 ? N : 1)) ++lg;
+        std::ostringstream k;
+        k << arch << "/nbox" << nbox << "/n2^" << lg << "/leaf" << params[0].leaf_max;
+        return k.str();
+    }
+
+    int autotune(const double* pos, const float* mass, float* acc, const char* cache_path,
+                 hipStream_t s) {
+        const std::string key = shape_key();
+        // cache lookup: one line per shape, "key chunk persistent waves graph"
+        if (cache_path) {
+            std::ifstream in(cache_path);
+            std::string line;
+            while (std::getline(in, line)) {
+                std::istringstream ls(line);
+                std::string k;
+                pp_tuning t{};
+                t.variant = tune.variant;
+                if (ls >> k >> t.chunk >> t.persistent >> t.waves_per_cu >> t.use_graph && k == key &&
+                    check_tuning_ok(t)) {
+                    tune = t;
+                    lists_valid = false;
+                    return PP_OK;
+                }
+            }
+        }
+        const bool batch = nbox > 1;
+        const int chunks[] = {1024, 2048, 4096, 8192};
+        struct Shape { int persistent, waves; };
+        const Shape shapes[] = {{0, 16}, {1, 8}, {1, 16}, {1, 32}};
+        pp_tuning best = tune;
+        float best_ms = 1e30f;
+        for (int c : chunks) {
+            for (const Shape& sh : shapes) {
+                pp_tuning t{c, sh.persistent, sh.waves, sh.persistent && batch ? 1 : 0, tune.variant};
+                tune = t;
+                float ms = 0.f;
+                PP_TRY(time_pp(pos, mass, acc, 3, s, &ms));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+        }
+        tune = best;
+        lists_valid = false;
+        if (cache_path) {
+            std::vector<std::string> keep;
+            {
+                std::ifstream in(cache_path);
+                std::string line;
+                while (std::getline(in, line))
+                    if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty()) keep.push_back(line);
+            }
+            std::ofstream out(cache_path, std::ios::trunc);
+            if (!out) return fail(PP_EINVAL, std::string("cannot write tuning cache ") + cache_path);
+            for (const std::string& l : keep) out << l << "\n";
+            out << key << " " << best.chunk << " " << best.persistent << " " << best.waves_per_cu
+                << " " << best.use_graph << "\n";
+        }
+        return PP_OK;
+    }
+
+    static bool check_tuning_ok(const pp_tuning& t) {
+        return t.chunk >= 64 && t.chunk <= (1 << 24) && t.chunk % 64 == 0 && t.waves_per_cu >= 1 &&
+               t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
+               t.variant <= 7;
+    }
+
+    int set_timing(int on) {
+        if (on && !ev0) {
+            PP_HIP(hipEventCreate(&ev0));
+            PP_HIP(hipEventCreate(&ev1));
+        }
+        timing = on != 0;
+        timed = false;
+        return PP_OK;
+    }
+};
+
+static int check_tuning(const pp_tuning* t) {
+    if (!t) return fail(PP_EINVAL, "tuning is NULL");
+    if (t->chunk < 64 || t->chunk > (1 << 24) || (t->chunk % 64) != 0)
+        return fail(PP_EINVAL, "chunk must be a multiple of 64 in 64..2^24");
+    if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
+    if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
+    if (t->variant < 0 || t->variant > 7) return fail(PP_EINVAL, "variant must be in 0..7");
+    return PP_OK;
+}
+
 }  // namespace pp
 
 using namespace pp;
 
 // ----------------------------------------------------------- objects --
 struct pp_leaves {
-    int64_t n = 0, m = 0;
-    pp_box_params p{};
-    DevBuf begin, count, level, prefix, boxes;
+    Batch b;
 };
 
 struct pp_pairs {
     int64_t nrows = 0, nentries = 0;
-    DevBuf row_cnt, row_ptr, src, code;
+    DevBuf row_cnt, row_ptr, src, code, scan_ws;
 };
 
 struct pp_plan {
-    pp_box_params p{};
-    Geo g{};
-    PolyF32 poly{};
-    int64_t n_max = 0;
-    int chunk = 4096;
-    // per-particle buffers
-    DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
-    DevBuf lam, pmax, smax, level_p, flag, flag_off;
-    DevBuf sort_ws, scan_ws;
-    size_t sort_ws_bytes = 0, scan_ws_bytes = 0;
-    // leaves + tree
-    DevBuf lbegin, lcount, llevel, lprefix, lboxes, tree_boxes;
-    TreeView tv{};
-    int64_t nleaf = 0;
-    BlockLists bl;
-    DevBuf partial, pcount, cnt_total;
-    pp_stats st{};
-    bool lists_valid = false;
-    int64_t last_n = 0;
-    bool timing = false, timed = false, evaluated_valid = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    ~pp_plan() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-    }
+    Batch b;
+};
+
+struct pp_batch_plan {
+    Batch b;
 };
 
 static hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -131,6 +441,13 @@ static int check_ptr(const void* p, int64_t n, const char* name) {
     if (n > 0 && !p) return fail(PP_EINVAL, std::string(name) + " is NULL");
     return PP_OK;
 }
+
+namespace {
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = (int32_t)k;
+}
+}  // namespace
 
 extern "C" {
 
@@ -156,25 +473,18 @@ int pp_hilbert_keys(const double* pos, int64_t n, double L, int key_bits, uint64
     if (!(std::isfinite(L) && L > 0)) return fail(PP_EINVAL, "L must be finite and > 0");
     if (key_bits < 1 || key_bits > 21) return fail(PP_EINVAL, "key_bits must be in 1..21");
     if (n == 0) return PP_OK;
-    return launch_keys(pos, n, L, key_bits, keys, nullptr, nullptr, S(stream));
+    return launch_keys_raw(pos, n, L, key_bits, keys, S(stream));
 }
 
 int pp_sort_workspace_size(int64_t n, size_t* bytes) {
     if (!bytes) return fail(PP_EINVAL, "bytes is NULL");
     if (n < 0 || n > INT32_MAX) return fail(PP_EINVAL, "n out of range");
     size_t b = 0;
-    PP_TRY(sort_workspace(n, 21, &b));
-    // plus the index sequence and key scratch the call fills itself
-    *bytes = b + 256 + sizeof(int32_t) * (size_t)n + 256;
+    PP_TRY(sort_workspace(n, 1, 21, &b));
+    // plus the index sequence the call fills itself
+    *bytes = ((b + 255) / 256) * 256 + sizeof(int32_t) * (size_t)n + 256;
     return PP_OK;
 }
-
-namespace {
-__global__ void iota_kernel(int32_t* p, int64_t n) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = (int32_t)k;
-}
-}  // namespace
 
 int pp_sort_by_key(const uint64_t* keys, int64_t n, int32_t* perm, uint64_t* sorted_keys, void* ws,
                    size_t ws_bytes, void* stream) {
@@ -190,7 +500,7 @@ int pp_sort_by_key(const uint64_t* keys, int64_t n, int32_t* perm, uint64_t* sor
         return fail(PP_EOVERFLOW, buf);
     }
     size_t sb = 0;
-    PP_TRY(sort_workspace(n, 21, &sb));
+    PP_TRY(sort_workspace(n, 1, 21, &sb));
     char* w = static_cast<char*>(ws);
     int32_t* idx = reinterpret_cast<int32_t*>(w + ((sb + 255) / 256) * 256);
     hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S(stream), idx,
@@ -202,7 +512,7 @@ int pp_sort_by_key(const uint64_t* keys, int64_t n, int32_t* perm, uint64_t* sor
         PP_TRY(tmp.reserve(sizeof(uint64_t) * n));
         kout = tmp.as<uint64_t>();
     }
-    PP_TRY(launch_sort(keys, idx, kout, perm, n, 21, w, sb, S(stream)));
+    PP_TRY(launch_sort_raw(keys, idx, kout, perm, n, 21, w, sb, S(stream)));
     if (!sorted_keys) PP_HIP(hipStreamSynchronize(S(stream)));   // before tmp is freed
     return PP_OK;
 }
@@ -211,33 +521,14 @@ int pp_build_leaves(const uint64_t* sorted_keys, const double* pos_sorted, int64
                     const pp_box_params* p, pp_leaves** out, void* stream) {
     if (!out) return fail(PP_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n < 0 || n > INT32_MAX) return fail(PP_EINVAL, "n out of range");
+    if (n < 0 || n > INT32_MAX - 4096) return fail(PP_EINVAL, "n out of range");
     PP_TRY(check_ptr(sorted_keys, n, "sorted_keys"));
     PP_TRY(check_ptr(pos_sorted, n, "pos_sorted"));
     PP_TRY(validate_params(p, false));
     pp_leaves* lv = new (std::nothrow) pp_leaves;
     if (!lv) return fail(PP_ENOMEM, "host allocation failed");
-    lv->n = n;
-    lv->p = *p;
-    const Geo g = make_geo(*p);
-    DevBuf lam, pmax, smax, level_p, flag, flag_off, scan_ws;
-    size_t sw = 0;
-    int rc = PP_OK;
-    const int64_t len = n + p->leaf_max + 1;
-    if ((rc = lam.reserve(len)) || (rc = pmax.reserve(len)) || (rc = smax.reserve(len)) ||
-        (rc = level_p.reserve(n + 1)) || (rc = flag.reserve(4 * (n + 1))) ||
-        (rc = flag_off.reserve(8 * (n + 2))) || (rc = scan_workspace(n, &sw)) ||
-        (rc = scan_ws.reserve(sw + 1))) {
-        delete lv;
-        return rc;
-    }
-    LeafBuffers lb{lam.as<int8_t>(), pmax.as<int8_t>(), smax.as<int8_t>(), level_p.as<int8_t>(),
-                   flag.as<int32_t>(), flag_off.as<int64_t>()};
-    // wrapped copy of the sorted positions is what the boxes use; the input
-    // is documented as already in key order, wrapping happens in quantise.
-    rc = build_leaves_device(sorted_keys, pos_sorted, n, g, p->leaf_max, lb, scan_ws.p,
-                             scan_ws.bytes, lv->begin, lv->count, lv->level, lv->prefix, lv->boxes,
-                             &lv->m, S(stream));
+    int rc = lv->b.init(1, p, &n, false);
+    if (rc == PP_OK) rc = stage_leaves(lv->b.bd, n, sorted_keys, pos_sorted, lv->b.w, S(stream));
     if (rc == PP_OK) {
         hipError_t e = hipStreamSynchronize(S(stream));
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
@@ -252,28 +543,29 @@ int pp_build_leaves(const uint64_t* sorted_keys, const double* pos_sorted, int64
 
 int pp_leaves_count(const pp_leaves* lv, int64_t* nleaf) {
     if (!lv || !nleaf) return fail(PP_EINVAL, "NULL argument");
-    *nleaf = lv->m;
+    *nleaf = lv->b.w.nleaf;
     return PP_OK;
 }
 
 int pp_leaves_export(const pp_leaves* lv, int64_t* begin, int32_t* count, int32_t* level,
                      uint64_t* prefix, int32_t* lo, int32_t* hi) {
     if (!lv) return fail(PP_EINVAL, "leaves is NULL");
-    const int64_t m = lv->m;
+    const Work& w = lv->b.w;
+    const int64_t m = w.nleaf;
     if (m == 0) return PP_OK;
-    if (begin) PP_HIP(hipMemcpy(begin, lv->begin.p, 8 * m, hipMemcpyDefault));
-    if (count) PP_HIP(hipMemcpy(count, lv->count.p, 4 * m, hipMemcpyDefault));
-    if (level) PP_HIP(hipMemcpy(level, lv->level.p, 4 * m, hipMemcpyDefault));
-    if (prefix) PP_HIP(hipMemcpy(prefix, lv->prefix.p, 8 * m, hipMemcpyDefault));
+    if (begin) PP_HIP(hipMemcpy(begin, w.lbegin.p, 8 * m, hipMemcpyDefault));
+    if (count) PP_HIP(hipMemcpy(count, w.lcount.p, 4 * m, hipMemcpyDefault));
+    if (level) PP_HIP(hipMemcpy(level, w.llevel.p, 4 * m, hipMemcpyDefault));
+    if (prefix) PP_HIP(hipMemcpy(prefix, w.lprefix.p, 8 * m, hipMemcpyDefault));
     if (lo || hi) {
         std::vector<IBox> hb(m);
-        PP_HIP(hipMemcpy(hb.data(), lv->boxes.p, sizeof(IBox) * m, hipMemcpyDeviceToHost));
+        PP_HIP(hipMemcpy(hb.data(), w.lboxes.p, sizeof(IBox) * m, hipMemcpyDeviceToHost));
         std::vector<int32_t> t(3 * m);
-        for (int w = 0; w < 2; ++w) {
-            int32_t* dst = w == 0 ? lo : hi;
+        for (int k = 0; k < 2; ++k) {
+            int32_t* dst = k == 0 ? lo : hi;
             if (!dst) continue;
             for (int64_t a = 0; a < m; ++a)
-                for (int ax = 0; ax < 3; ++ax) t[ax * m + a] = w == 0 ? hb[a].lo[ax] : hb[a].hi[ax];
+                for (int ax = 0; ax < 3; ++ax) t[ax * m + a] = k == 0 ? hb[a].lo[ax] : hb[a].hi[ax];
             PP_HIP(hipMemcpy(dst, t.data(), 4 * 3 * m, hipMemcpyDefault));
         }
     }
@@ -282,25 +574,21 @@ int pp_leaves_export(const pp_leaves* lv, int64_t* begin, int32_t* count, int32_
 
 void pp_leaves_free(pp_leaves* lv) { delete lv; }
 
-int pp_near_pairs(const pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* stream) {
+int pp_near_pairs(pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* stream) {
     if (!out) return fail(PP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!lv) return fail(PP_EINVAL, "leaves is NULL");
     PP_TRY(validate_params(p, false));
-    if (p->key_bits != lv->p.key_bits || p->L != lv->p.L)
+    const pp_box_params& lp = lv->b.params[0];
+    if (p->key_bits != lp.key_bits || p->L != lp.L)
         return fail(PP_EINVAL, "params do not match the leaves (L, key_bits)");
     pp_pairs* pr = new (std::nothrow) pp_pairs;
     if (!pr) return fail(PP_ENOMEM, "host allocation failed");
-    const Geo g = make_geo(*p);
-    DevBuf tree, scan_ws;
-    TreeView tv{};
-    size_t sw = 0;
-    int rc = scan_workspace(lv->m, &sw);
-    if (rc == PP_OK) rc = scan_ws.reserve(sw + 1);
-    if (rc == PP_OK && lv->m > 0) rc = build_tree(lv->boxes.as<IBox>(), lv->m, tree, &tv, S(stream));
+    const BoxDev g = make_boxdev(*p, 0, lv->b.N);
+    int rc = stage_trees(lv->b.bd, lv->b.w, S(stream));
     if (rc == PP_OK)
-        rc = build_canonical_pairs(tv, lv->m, g, pr->row_cnt, pr->row_ptr, pr->src, pr->code,
-                                   scan_ws.p, scan_ws.bytes, &pr->nentries, S(stream));
+        rc = build_canonical_pairs(lv->b.bd, lv->b.w, g.W, g.T, pr->row_cnt, pr->row_ptr, pr->src,
+                                   pr->code, pr->scan_ws, &pr->nentries, S(stream));
     if (rc == PP_OK) {
         hipError_t e = hipStreamSynchronize(S(stream));
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
@@ -309,7 +597,7 @@ int pp_near_pairs(const pp_leaves* lv, const pp_box_params* p, pp_pairs** out, v
         delete pr;
         return rc;
     }
-    pr->nrows = lv->m;
+    pr->nrows = lv->b.w.nleaf;
     *out = pr;
     return PP_OK;
 }
@@ -333,94 +621,42 @@ int pp_pairs_export(const pp_pairs* pr, int64_t* row_ptr, int32_t* src_leaf, uin
 
 void pp_pairs_free(pp_pairs* pr) { delete pr; }
 
+// ---------------------------------------------------------------- plans --
 int pp_plan_create(const pp_box_params* p, int64_t n_max, pp_plan** out) {
     if (!out) return fail(PP_EINVAL, "out is NULL");
     *out = nullptr;
     PP_TRY(validate_params(p, true));
-    if (n_max < 0 || n_max > INT32_MAX - 2048) return fail(PP_EINVAL, "n_max out of range");
-    int dev_count = 0;
-    hipError_t e = hipGetDeviceCount(&dev_count);
-    if (e != hipSuccess || dev_count == 0) {
-        (void)hipGetLastError();
-        return fail(PP_EDEVICE, "no HIP device available");
-    }
+    if (n_max < 0 || n_max > INT32_MAX - 4096) return fail(PP_EINVAL, "n_max out of range");
     pp_plan* pl = new (std::nothrow) pp_plan;
     if (!pl) return fail(PP_ENOMEM, "host allocation failed");
-    pl->p = *p;
-    pl->g = make_geo(*p);
-    make_poly(*p, &pl->poly);
-    pl->n_max = n_max;
-    const int64_t n = n_max > 0 ? n_max : 1;
-    const int M = p->leaf_max;
-    int rc = PP_OK;
-    size_t sw = 0, cw = 0;
-    if ((rc = pl->keys.reserve(8 * n)) || (rc = pl->keys_s.reserve(8 * n)) ||
-        (rc = pl->iota.reserve(4 * n)) || (rc = pl->perm.reserve(4 * n)) ||
-        (rc = pl->pos_s.reserve(24 * n)) || (rc = pl->mass_s.reserve(4 * n)) ||
-        (rc = pl->bad.reserve(64)) || (rc = pl->lam.reserve(n + M + 1)) ||
-        (rc = pl->pmax.reserve(n + M + 1)) || (rc = pl->smax.reserve(n + M + 1)) ||
-        (rc = pl->level_p.reserve(n + 1)) || (rc = pl->flag.reserve(4 * (n + 1))) ||
-        (rc = pl->flag_off.reserve(8 * (n + 2))) || (rc = sort_workspace(n, p->key_bits, &sw)) ||
-        (rc = pl->sort_ws.reserve(sw + 1)) || (rc = scan_workspace(n + 1, &cw)) ||
-        (rc = pl->scan_ws.reserve(cw + 1)) || (rc = pl->cnt_total.reserve(64))) {
+    int rc = pl->b.init(1, p, &n_max);
+    if (rc != PP_OK) {
         delete pl;
         return rc;
     }
-    pl->sort_ws_bytes = pl->sort_ws.bytes;
-    pl->scan_ws_bytes = pl->scan_ws.bytes;
     *out = pl;
     return PP_OK;
 }
 
 void pp_plan_destroy(pp_plan* plan) { delete plan; }
 
-// Stages shared by the FP32 and FP64 paths: keys, sort, gather, leaves,
-// tree and block lists.  Synchronises the stream.
-static int prepare(pp_plan* pl, const double* pos, const float* mass_f, const double* mass_d,
-                   int64_t n, hipStream_t s) {
-    pl->lists_valid = false;
-    pl->evaluated_valid = false;
-    PP_HIP(hipMemsetAsync(pl->bad.p, 0, sizeof(int), s));
-    PP_TRY(launch_keys(pos, n, pl->p.L, pl->p.key_bits, pl->keys.as<uint64_t>(),
-                       pl->iota.as<int32_t>(), pl->bad.as<int>(), s));
-    PP_TRY(launch_sort(pl->keys.as<uint64_t>(), pl->iota.as<int32_t>(), pl->keys_s.as<uint64_t>(),
-                       pl->perm.as<int32_t>(), n, pl->p.key_bits, pl->sort_ws.p, pl->sort_ws_bytes,
-                       s));
-    if (mass_d) PP_TRY(pl->mass_sd.reserve(8 * (n > 0 ? n : 1)));
-    PP_TRY(launch_gather(pos, mass_f, mass_d, pl->perm.as<int32_t>(), n, pl->p.L,
-                         pl->pos_s.as<double>(), pl->mass_s.as<float>(),
-                         mass_d ? pl->mass_sd.as<double>() : nullptr, pl->bad.as<int>(), s));
-    LeafBuffers lb{pl->lam.as<int8_t>(), pl->pmax.as<int8_t>(), pl->smax.as<int8_t>(),
-                   pl->level_p.as<int8_t>(), pl->flag.as<int32_t>(), pl->flag_off.as<int64_t>()};
-    PP_TRY(build_leaves_device(pl->keys_s.as<uint64_t>(), pl->pos_s.as<double>(), n, pl->g,
-                               pl->p.leaf_max, lb, pl->scan_ws.p, pl->scan_ws_bytes, pl->lbegin,
-                               pl->lcount, pl->llevel, pl->lprefix, pl->lboxes, &pl->nleaf, s));
-    int bad = 0;
-    PP_HIP(hipMemcpyAsync(&bad, pl->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    PP_HIP(hipStreamSynchronize(s));
-    if (bad) return fail(PP_EINVAL, "non-finite position or mass");
-    PP_TRY(build_tree(pl->lboxes.as<IBox>(), pl->nleaf, pl->tree_boxes, &pl->tv, s));
-    PP_TRY(build_block_lists(pl->pos_s.as<double>(), n, pl->lbegin.as<int64_t>(),
-                             pl->lcount.as<int32_t>(), pl->tv, pl->nleaf, pl->g, pl->chunk,
-                             pl->p.rcut, pl->bl, pl->scan_ws, s));
-    pl->scan_ws_bytes = pl->scan_ws.bytes;
-    pl->st.n = n;
-    pl->st.nleaf = pl->nleaf;
-    pl->st.nblock = pl->bl.nblock;
-    pl->st.nrange = pl->bl.nrange;
-    pl->st.nitem = pl->bl.nitem;
-    pl->st.candidates = pl->bl.candidates;
-    pl->st.interactions = -1;
-    pl->st.pp_kernel_ms = -1.0;
-    pl->lists_valid = true;
-    pl->last_n = n;
+// A plan holds one box of up to n_max particles; a call with n < n_max
+// describes the box again with n particles.
+static int plan_resize(pp_plan* pl, int64_t n) {
+    Batch& b = pl->b;
+    if (b.poff[1] == n) return PP_OK;
+    b.poff[1] = n;
+    b.N = n;
+    const BoxDev hb = make_boxdev(b.params[0], 0, n);
+    PP_HIP(hipMemcpy(b.box_dev.p, &hb, sizeof(BoxDev), hipMemcpyHostToDevice));
+    PP_HIP(hipMemcpy(b.poff_dev.p, b.poff.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice));
     return PP_OK;
 }
 
 static int check_accel_args(pp_plan* pl, const void* pos, const void* mass, int64_t n,
                             const void* acc) {
     if (!pl) return fail(PP_EINVAL, "plan is NULL");
-    if (n < 0 || n > pl->n_max) return fail(PP_EINVAL, "n must be in 0..n_max of the plan");
+    if (n < 0 || n > pl->b.n_max) return fail(PP_EINVAL, "n must be in 0..n_max of the plan");
     PP_TRY(check_ptr(pos, n, "pos"));
     PP_TRY(check_ptr(mass, n, "mass"));
     PP_TRY(check_ptr(acc, n, "acc"));
@@ -431,92 +667,159 @@ int pp_accel(pp_plan* pl, const double* pos, const float* mass, int64_t n, float
              void* stream) {
     PP_TRY(check_accel_args(pl, pos, mass, n, acc));
     if (n == 0) return PP_OK;
+    PP_TRY(plan_resize(pl, n));
     hipStream_t s = S(stream);
-    PP_TRY(prepare(pl, pos, mass, nullptr, n, s));
-    PP_TRY(pl->partial.reserve(sizeof(float) * 6 * kBlock * (pl->bl.nitem + 1)));
-    unsigned long long* evald = reinterpret_cast<unsigned long long*>(pl->cnt_total.as<char>() + 8);
-    PP_HIP(hipMemsetAsync(evald, 0, 2 * sizeof(unsigned long long), s));
-    pl->evaluated_valid = true;
-    if (pl->timing) PP_HIP(hipEventRecord(pl->ev0, s));
-    PP_TRY(launch_pp_f32(pl->bl, pl->pos_s.as<double>(), pl->mass_s.as<float>(), n, pl->p, pl->poly,
-                         pl->chunk, pl->partial.as<float>(), evald, s));
-    if (pl->timing) {
-        PP_HIP(hipEventRecord(pl->ev1, s));
-        pl->timed = true;
-    }
-    const double scale = pl->p.G / (pl->p.rcut * pl->p.rcut);
-    PP_TRY(launch_reduce_f32(pl->bl, pl->partial.as<float>(), pl->perm.as<int32_t>(), n, scale, acc,
-                             s));
-    return PP_OK;
+    PP_TRY(pl->b.prepare(pos, mass, nullptr, s));
+    return pl->b.run_f32(acc, s);
 }
 
 int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, double* acc,
                  void* stream) {
     PP_TRY(check_accel_args(pl, pos, mass, n, acc));
     if (n == 0) return PP_OK;
+    PP_TRY(plan_resize(pl, n));
     hipStream_t s = S(stream);
-    PP_TRY(prepare(pl, pos, nullptr, mass, n, s));
-    PP_TRY(pl->partial.reserve(sizeof(double) * 3 * kBlock * (pl->bl.nitem + 1)));
-    if (pl->timing) PP_HIP(hipEventRecord(pl->ev0, s));
-    PP_TRY(launch_pp_f64(pl->bl, pl->pos_s.as<double>(), pl->mass_sd.as<double>(), n, pl->p,
-                         pl->chunk, pl->partial.as<double>(), s));
-    if (pl->timing) {
-        PP_HIP(hipEventRecord(pl->ev1, s));
-        pl->timed = true;
+    Batch& b = pl->b;
+    PP_TRY(b.prepare(pos, nullptr, mass, s));
+    PP_TRY(b.partial.reserve(sizeof(double) * 3 * kBlock * (b.w.nitem + 1)));
+    if (b.timing) PP_HIP(hipEventRecord(b.ev0, s));
+    PP_TRY(launch_pp_f64(b.bd, b.w, b.w.chunk, reinterpret_cast<double*>(b.partial.p), s));
+    if (b.timing) {
+        PP_HIP(hipEventRecord(b.ev1, s));
+        b.timed = true;
     }
-    PP_TRY(launch_reduce_f64(pl->bl, pl->partial.as<double>(), pl->perm.as<int32_t>(), n, acc, s));
+    PP_TRY(launch_reduce_f64(b.bd, b.w, reinterpret_cast<double*>(b.partial.p), acc, s));
     return PP_OK;
 }
 
 int pp_plan_stats(pp_plan* pl, pp_stats* out) {
     if (!pl || !out) return fail(PP_EINVAL, "NULL argument");
-    pl->st.pp_kernel_ms = -1.0;
-    if (pl->timing && pl->timed) {
-        PP_HIP(hipEventSynchronize(pl->ev1));
-        float ms = 0.f;
-        PP_HIP(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
-        pl->st.pp_kernel_ms = ms;
-    }
-    pl->st.evaluated = -1;
-    pl->st.lane_pairs = -1;
-    if (pl->evaluated_valid) {
-        unsigned long long h[2] = {0, 0};
-        PP_HIP(hipMemcpy(h, pl->cnt_total.as<char>() + 8, sizeof(h), hipMemcpyDeviceToHost));
-        pl->st.evaluated = (int64_t)h[0];
-        pl->st.lane_pairs = (int64_t)h[1];
-    }
-    *out = pl->st;
-    return PP_OK;
+    return pl->b.stats(out);
 }
 
 int pp_plan_set_timing(pp_plan* pl, int on) {
     if (!pl) return fail(PP_EINVAL, "plan is NULL");
-    if (on && !pl->ev0) {
-        PP_HIP(hipEventCreate(&pl->ev0));
-        PP_HIP(hipEventCreate(&pl->ev1));
-    }
-    pl->timing = on != 0;
-    pl->timed = false;
+    return pl->b.set_timing(on);
+}
+
+int pp_plan_get_tuning(const pp_plan* pl, pp_tuning* t) {
+    if (!pl || !t) return fail(PP_EINVAL, "NULL argument");
+    *t = pl->b.tune;
+    return PP_OK;
+}
+
+int pp_plan_set_tuning(pp_plan* pl, const pp_tuning* t) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    PP_TRY(check_tuning(t));
+    pl->b.tune = *t;
+    pl->b.lists_valid = false;
+    return PP_OK;
+}
+
+static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStream_t s) {
+    if (!b.lists_valid) return fail(PP_EINVAL, "no lists: call the accel function first");
+    PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.nitem + 1)));
+    PP_TRY(launch_count(b.bd, b.w, b.w.chunk, b.pcount.as<int32_t>(), s));
+    unsigned long long* tot = b.w.misc.as<unsigned long long>() + 4;
+    PP_HIP(hipMemsetAsync(tot, 0, sizeof(unsigned long long), s));
+    PP_TRY(launch_reduce_count(b.bd, b.w, b.pcount.as<int32_t>(), counts, tot, s));
+    unsigned long long h = 0;
+    PP_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    *total = (int64_t)h;
+    b.st.interactions = (int64_t)h;
     return PP_OK;
 }
 
 int pp_count_interactions(pp_plan* pl, int64_t* counts, int64_t* total, void* stream) {
     if (!pl || !total) return fail(PP_EINVAL, "NULL argument");
-    if (!pl->lists_valid) return fail(PP_EINVAL, "no lists: call pp_accel first");
-    const int64_t n = pl->last_n;
+    return count_interactions(pl->b, counts, total, S(stream));
+}
+
+// -------------------------------------------------------------- batches --
+int pp_batch_plan_create(int nbox, const pp_box_params* params, const int64_t* n,
+                         pp_batch_plan** out) {
+    if (!out) return fail(PP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nbox < 1 || nbox > 65536) return fail(PP_EINVAL, "nbox must be in 1..65536");
+    if (!params || !n) return fail(PP_EINVAL, "params or n is NULL");
+    pp_batch_plan* bp = new (std::nothrow) pp_batch_plan;
+    if (!bp) return fail(PP_ENOMEM, "host allocation failed");
+    bp->b.tune.persistent = 1;
+    bp->b.tune.use_graph = 1;
+    int rc = bp->b.init(nbox, params, n);
+    if (rc != PP_OK) {
+        delete bp;
+        return rc;
+    }
+    *out = bp;
+    return PP_OK;
+}
+
+void pp_batch_plan_destroy(pp_batch_plan* bp) { delete bp; }
+
+int pp_batch_accel(pp_batch_plan* bp, const double* pos, const float* mass, float* acc,
+                   void* stream) {
+    if (!bp) return fail(PP_EINVAL, "plan is NULL");
+    Batch& b = bp->b;
+    PP_TRY(check_ptr(pos, b.N, "pos"));
+    PP_TRY(check_ptr(mass, b.N, "mass"));
+    PP_TRY(check_ptr(acc, b.N, "acc"));
+    if (b.N == 0) return PP_OK;
     hipStream_t s = S(stream);
-    PP_TRY(pl->pcount.reserve(sizeof(int32_t) * kBlock * (pl->bl.nitem + 1)));
-    PP_TRY(launch_count(pl->bl, pl->pos_s.as<double>(), n, pl->p, pl->chunk,
-                        pl->pcount.as<int32_t>(), s));
-    unsigned long long* tot = reinterpret_cast<unsigned long long*>(pl->cnt_total.p);
-    PP_HIP(hipMemsetAsync(tot, 0, sizeof(unsigned long long), s));
-    PP_TRY(launch_reduce_count(pl->bl, pl->pcount.as<int32_t>(), pl->perm.as<int32_t>(), n, counts,
-                               tot, s));
-    unsigned long long h = 0;
-    PP_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
-    PP_HIP(hipStreamSynchronize(s));
-    *total = (int64_t)h;
-    pl->st.interactions = (int64_t)h;
+    PP_TRY(b.prepare(pos, mass, nullptr, s));
+    return b.run_f32(acc, s);
+}
+
+int pp_batch_count_interactions(pp_batch_plan* bp, int64_t* counts, int64_t* total, void* stream) {
+    if (!bp || !total) return fail(PP_EINVAL, "NULL argument");
+    return count_interactions(bp->b, counts, total, S(stream));
+}
+
+int pp_batch_stats(pp_batch_plan* bp, pp_stats* out) {
+    if (!bp || !out) return fail(PP_EINVAL, "NULL argument");
+    return bp->b.stats(out);
+}
+
+int pp_batch_set_timing(pp_batch_plan* bp, int on) {
+    if (!bp) return fail(PP_EINVAL, "plan is NULL");
+    return bp->b.set_timing(on);
+}
+
+int pp_batch_get_tuning(const pp_batch_plan* bp, pp_tuning* t) {
+    if (!bp || !t) return fail(PP_EINVAL, "NULL argument");
+    *t = bp->b.tune;
+    return PP_OK;
+}
+
+int pp_autotune(pp_plan* pl, const double* pos, const float* mass, int64_t n, const char* cache_path,
+                void* stream) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    if (n <= 0 || n > pl->b.n_max) return fail(PP_EINVAL, "n must be in 1..n_max of the plan");
+    PP_TRY(check_ptr(pos, n, "pos"));
+    PP_TRY(check_ptr(mass, n, "mass"));
+    PP_TRY(plan_resize(pl, n));
+    DevBuf acc;
+    PP_TRY(acc.reserve(sizeof(float) * 3 * n));
+    return pl->b.autotune(pos, mass, acc.as<float>(), cache_path, S(stream));
+}
+
+int pp_batch_autotune(pp_batch_plan* bp, const double* pos, const float* mass,
+                      const char* cache_path, void* stream) {
+    if (!bp) return fail(PP_EINVAL, "plan is NULL");
+    if (bp->b.N == 0) return PP_OK;
+    PP_TRY(check_ptr(pos, bp->b.N, "pos"));
+    PP_TRY(check_ptr(mass, bp->b.N, "mass"));
+    DevBuf acc;
+    PP_TRY(acc.reserve(sizeof(float) * 3 * bp->b.N));
+    return bp->b.autotune(pos, mass, acc.as<float>(), cache_path, S(stream));
+}
+
+int pp_batch_set_tuning(pp_batch_plan* bp, const pp_tuning* t) {
+    if (!bp) return fail(PP_EINVAL, "plan is NULL");
+    PP_TRY(check_tuning(t));
+    bp->b.tune = *t;
+    bp->b.lists_valid = false;
     return PP_OK;
 }
 

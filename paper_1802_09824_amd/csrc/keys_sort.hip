@@ -6,11 +6,13 @@
 // index by undoing reflections and axis exchanges from the coarsest level
 // down, Gray-encoding across axes, and interleaving with x as the most
 // significant bit of every 3-bit digit.  The sort makes every octree node a
-// contiguous run of particles (sec. 3.2).
+// contiguous run of particles (sec. 3.2); in a batch each box is sorted as
+// its own segment.
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
 
 #include "pp_internal.h"
@@ -53,8 +55,7 @@ __device__ __forceinline__ uint64_t hilbert_index(uint32_t x, uint32_t y, uint32
     // of that axis and axis 0 are exchanged.
     for (uint32_t Q = top; Q > 1; Q >>= 1) {
         const uint32_t P = Q - 1;
-        // axis 0 (its exchange with itself is a no-op)
-        if (X0 & Q) X0 ^= P;
+        if (X0 & Q) X0 ^= P;               // axis 0 (its exchange with itself is a no-op)
         if (X1 & Q) {
             X0 ^= P;
         } else {
@@ -82,36 +83,49 @@ __device__ __forceinline__ uint64_t hilbert_index(uint32_t x, uint32_t y, uint32
     return (spread3(X0) << 2) | (spread3(X1) << 1) | spread3(X2);
 }
 
-__global__ void __launch_bounds__(256) keys_kernel(const double* __restrict__ pos, int64_t n,
-                                                   double L, double scale, int b, uint32_t qmax,
-                                                   uint64_t* __restrict__ keys,
+__device__ __forceinline__ uint64_t key_of(double x, double y, double z, double L, double scale,
+                                           int b) {
+    const uint32_t qmax = (1u << b) - 1u;
+    return hilbert_index(quantise(wrap_pos(x, L), scale, qmax), quantise(wrap_pos(y, L), scale, qmax),
+                         quantise(wrap_pos(z, L), scale, qmax), b);
+}
+
+__global__ void __launch_bounds__(256) keys_kernel(BatchDev bd, const double* __restrict__ pos,
+                                                   int64_t N, uint64_t* __restrict__ keys,
                                                    int32_t* __restrict__ iota, int* bad) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double x = pos[k], y = pos[n + k], z = pos[2 * n + k];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const BoxDev& B = bd.box[box_of(bd.poff, bd.nbox, k)];
+    double x = pos[k], y = pos[N + k], z = pos[2 * N + k];
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
         atomicOr(bad, 1);
         x = y = z = 0.0;
     }
-    uint32_t qx = quantise(wrap_pos(x, L), scale, qmax);
-    uint32_t qy = quantise(wrap_pos(y, L), scale, qmax);
-    uint32_t qz = quantise(wrap_pos(z, L), scale, qmax);
-    keys[k] = hilbert_index(qx, qy, qz, b);
-    if (iota) iota[k] = (int32_t)k;
+    keys[k] = key_of(x, y, z, B.L, B.qscale, bd.bits);
+    iota[k] = (int32_t)k;
+}
+
+__global__ void __launch_bounds__(256) keys_raw_kernel(const double* __restrict__ pos, int64_t n,
+                                                       double L, double scale, int b,
+                                                       uint64_t* __restrict__ keys) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    keys[k] = key_of(pos[k], pos[n + k], pos[2 * n + k], L, scale, b);
 }
 
 template <class M>
-__global__ void __launch_bounds__(256) gather_kernel(const double* __restrict__ pos,
+__global__ void __launch_bounds__(256) gather_kernel(BatchDev bd, const double* __restrict__ pos,
                                                      const M* __restrict__ mass,
-                                                     const int32_t* __restrict__ perm, int64_t n,
-                                                     double L, double* __restrict__ pos_s,
+                                                     const int32_t* __restrict__ perm, int64_t N,
+                                                     double* __restrict__ pos_s,
                                                      M* __restrict__ mass_s, int* bad) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int64_t i = perm[k];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double L = bd.box[box_of(bd.poff, bd.nbox, k)].L;
+    const int64_t i = perm[k];
     for (int a = 0; a < 3; ++a) {
-        double x = pos[a * n + i];
-        pos_s[a * n + k] = isfinite(x) ? wrap_pos(x, L) : 0.0;
+        const double x = pos[a * N + i];
+        pos_s[a * N + k] = isfinite(x) ? wrap_pos(x, L) : 0.0;
     }
     M m = mass[i];
     if (!isfinite((double)m)) {
@@ -127,32 +141,44 @@ struct to_i64 {
     __device__ __host__ int64_t operator()(int32_t v) const { return (int64_t)v; }
 };
 
-inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
-
 }  // namespace
 
-int launch_keys(const double* pos, int64_t n, double L, int bits, uint64_t* keys, int32_t* iota,
-                int* bad_flag, hipStream_t s) {
-    if (n == 0) return PP_OK;
-    const double scale = ldexp(1.0, bits) / L;
-    const uint32_t qmax = (1u << bits) - 1u;
-    hipLaunchKernelGGL(keys_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, n, L, scale,
-                       bits, qmax, keys, iota, bad_flag);
+int stage_keys(const BatchDev& bd, int64_t N, const double* pos, Work& w, hipStream_t s) {
+    if (N == 0) return PP_OK;
+    hipLaunchKernelGGL(keys_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos, N,
+                       w.keys.as<uint64_t>(), w.iota.as<int32_t>(), w.bad.as<int>());
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int sort_workspace(int64_t n, int bits, size_t* bytes) {
+int launch_keys_raw(const double* pos, int64_t n, double L, int bits, uint64_t* keys,
+                    hipStream_t s) {
+    if (n == 0) return PP_OK;
+    hipLaunchKernelGGL(keys_raw_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, n, L,
+                       ldexp(1.0, bits) / L, bits, keys);
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
+int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes) {
     size_t b = 0;
-    PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                     (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0,
-                                     3 * bits, (hipStream_t)0));
+    if (nbox <= 1) {
+        PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b, (const uint64_t*)nullptr,
+                                         (uint64_t*)nullptr, (const int32_t*)nullptr,
+                                         (int32_t*)nullptr, (size_t)n, 0, 3 * bits, (hipStream_t)0));
+    } else {
+        PP_HIP(rocprim::segmented_radix_sort_pairs(
+            (void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, (const int32_t*)nullptr,
+            (int32_t*)nullptr, (unsigned)n, (unsigned)nbox, (const int64_t*)nullptr,
+            (const int64_t*)nullptr, 0, 3 * bits, (hipStream_t)0));
+    }
     *bytes = b;
     return PP_OK;
 }
 
-int launch_sort(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out, int32_t* perm_out,
-                int64_t n, int bits, void* ws, size_t ws_bytes, hipStream_t s) {
+int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out,
+                    int32_t* perm_out, int64_t n, int bits, void* ws, size_t ws_bytes,
+                    hipStream_t s) {
     if (n == 0) return PP_OK;
     size_t b = ws_bytes;
     PP_HIP(rocprim::radix_sort_pairs(ws, b, keys, keys_out, idx_in, perm_out, (size_t)n, 0, 3 * bits,
@@ -160,16 +186,36 @@ int launch_sort(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out,
     return PP_OK;
 }
 
-int launch_gather(const double* pos, const float* mass_f, const double* mass_d,
-                  const int32_t* perm, int64_t n, double L, double* pos_s, float* mass_s_f,
-                  double* mass_s_d, int* bad_flag, hipStream_t s) {
-    if (n == 0) return PP_OK;
+int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
+    if (N == 0) return PP_OK;
+    size_t need = 0;
+    PP_TRY(sort_workspace(N, bd.nbox, bd.bits, &need));
+    PP_TRY(w.sort_ws.reserve(need + 1));
+    size_t b = w.sort_ws.bytes;
+    if (bd.nbox <= 1) {
+        PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, w.keys.as<uint64_t>(),
+                                         w.keys_s.as<uint64_t>(), w.iota.as<int32_t>(),
+                                         w.perm.as<int32_t>(), (size_t)N, 0, 3 * bd.bits, s));
+    } else {
+        PP_HIP(rocprim::segmented_radix_sort_pairs(
+            w.sort_ws.p, b, w.keys.as<uint64_t>(), w.keys_s.as<uint64_t>(), w.iota.as<int32_t>(),
+            w.perm.as<int32_t>(), (unsigned)N, (unsigned)bd.nbox, bd.poff, bd.poff + 1, 0,
+            3 * bd.bits, s));
+    }
+    return PP_OK;
+}
+
+int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* mass_f,
+                 const double* mass_d, Work& w, hipStream_t s) {
+    if (N == 0) return PP_OK;
     if (mass_f)
-        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos,
-                           mass_f, perm, n, L, pos_s, mass_s_f, bad_flag);
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos,
+                           mass_f, w.perm.as<int32_t>(), N, w.pos_s.as<double>(),
+                           w.mass_s.as<float>(), w.bad.as<int>());
     else
-        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos,
-                           mass_d, perm, n, L, pos_s, mass_s_d, bad_flag);
+        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd,
+                           pos, mass_d, w.perm.as<int32_t>(), N, w.pos_s.as<double>(),
+                           w.mass_sd.as<double>(), w.bad.as<int>());
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
@@ -183,14 +229,20 @@ int scan_workspace(int64_t n, size_t* bytes) {
     return PP_OK;
 }
 
-int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, void* ws, size_t ws_bytes,
-                           hipStream_t s) {
+int grow_scan(DevBuf& buf, int64_t n) {
+    size_t need = 0;
+    PP_TRY(scan_workspace(n, &need));
+    return buf.reserve(need + 1);
+}
+
+int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s) {
     hipLaunchKernelGGL(set_zero_i64, dim3(1), dim3(1), 0, s, off);
     PP_HIP(hipGetLastError());
     if (n == 0) return PP_OK;
-    size_t b = ws_bytes;
+    PP_TRY(grow_scan(ws, n));
+    size_t b = ws.bytes;
     rocprim::transform_iterator<const int32_t*, to_i64, int64_t> it(in, to_i64());
-    PP_HIP(rocprim::inclusive_scan(ws, b, it, off + 1, (size_t)n, rocprim::plus<int64_t>(), s));
+    PP_HIP(rocprim::inclusive_scan(ws.p, b, it, off + 1, (size_t)n, rocprim::plus<int64_t>(), s));
     return PP_OK;
 }
 

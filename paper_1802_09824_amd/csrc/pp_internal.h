@@ -1,5 +1,9 @@
 // Internal declarations shared by the library's translation units.
 // Nothing here is part of the C ABI (include/photon_pp.h is).
+//
+// Every stage works on a *batch*: nbox independent periodic boxes whose
+// particles are concatenated (box x owns particles [poff[x], poff[x+1])).
+// A single box is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,7 +35,8 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line);
     } while (0)
 
 // --------------------------------------------------------- device memory --
-// Grow-only device buffer.  Contents are not preserved across growth.
+// Grow-only device buffer.  Contents are not preserved across growth; every
+// growth bumps a global generation so cached graphs can notice.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -43,6 +48,21 @@ struct DevBuf {
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
 };
+uint64_t alloc_generation();
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <class T>
+int read_back(const T* dev, T* host, hipStream_t s) {
+    PP_HIP(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    return PP_OK;
+}
+
+// Target blocks: runs of at most kBlock consecutive particles (key order)
+// inside one kBlock-particle chunk of one box whose bounding box side stays
+// within 2 r_cut (so FP32 offsets from the block centre stay small).
+constexpr int kBlock = 64;
 
 // Integer bounding box of grid cells, hi exclusive.  Grid units: the box is
 // W = 2^b cells wide, coordinates fit int32.
@@ -51,119 +71,133 @@ struct IBox {
     int32_t hi[3];
 };
 
-// Implicit 8-ary tree over the leaf array: level 0 holds the leaf boxes,
-// node i of level h covers nodes 8i..8i+7 of level h-1.
+// Implicit 8-ary tree over one box's leaves: level 0 holds the leaf boxes,
+// node i of level h covers nodes 8i..8i+7 of level h-1.  Node (h, i) is
+// element off[h] + i of the shared node-box array; node indices are local
+// to the box (leaf i of the box is global leaf loff + i).
 constexpr int kTreeMaxLevels = 16;
 struct TreeView {
-    const IBox* box;                 // all levels, level h at off[h]
     int64_t off[kTreeMaxLevels];
     int64_t cnt[kTreeMaxLevels];
-    int nlev;
+    int64_t loff;
+    int32_t nlev;
+    int32_t pad;
 };
 
-// ------------------------------------------------------- geometry params --
-struct Geo {
-    double L;           // box side
-    int bits;           // key bits per axis
-    int64_t W;          // 2^bits
-    int64_t T;          // ceil(r^2), r = rcut * W / L (grid units)
-    double qscale;      // 2^bits / L
+// FP32 constants of the PP kernel for one box (units of r_cut).
+struct PolyF32 {
+    float c[10];     // k^3 H coefficients in t, highest last
+    float tscale;    // t = r2 * tscale - 1
+    float eps2n;     // softening^2 / rcut^2 (floored)
+    float cut2;      // 1 + eps2n
+    float pad;
 };
-Geo make_geo(const pp_box_params& p);
 
-// Validation shared by the entry points; returns PP_OK or an error code.
+// Per-box constants, resident on the device.
+struct BoxDev {
+    double L, qscale, cell, inv_rcut, scale;   // scale = G / rcut^2
+    double rs, rcut, eps, G;
+    int64_t W, T, emax;
+    int64_t poff, n;
+    PolyF32 poly;
+};
+
+int make_poly(const pp_box_params& p, PolyF32* out);
+BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n);
 int validate_params(const pp_box_params* p, bool need_poly);
+
+// Box of particle (or chunk, leaf, ...) k given ascending start offsets:
+// the last x with off[x] <= k (empty boxes are skipped naturally).
+__device__ __forceinline__ int box_of(const int64_t* __restrict__ off, int nbox, int64_t k) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Device view of a batch shared by the kernels.
+struct BatchDev {
+    const BoxDev* box;       // [nbox]
+    const int64_t* poff;     // [nbox + 1] particle offsets
+    int nbox;
+    int bits;                // key bits per axis (shared)
+    int leaf_max;            // shared
+};
+
+// ------------------------------------------------------------- workspace --
+struct Work {
+    int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
+    // particles
+    DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
+    DevBuf sort_ws, scan_ws;
+    // leaves
+    DevBuf lam, pmax, smax, level_p, flag, flag_off;
+    DevBuf lbegin, lcount, llevel, lprefix, lboxes, loff_dev;
+    int64_t nleaf = 0;
+    std::vector<int64_t> loff;            // host copy [nbox + 1]
+    // trees
+    DevBuf tree_boxes, tviews, lvl_prefix;
+    std::vector<TreeView> tv;             // host copy [nbox]
+    int max_levels = 0;
+    // blocks, lists, items
+    int64_t nchunk = 0, nblock = 0, nentry = 0, nrange = 0, nitem = 0;
+    int64_t candidates = 0;
+    int chunk = 0;           // effective chunk of the current items (>= the requested one)
+    DevBuf choff, ccount, coff;
+    DevBuf bstart, bcount, bbox, bboxid;
+    DevBuf fent_a, fent_b, fcnt, foff;
+    DevBuf lmask_e, rcnt_e, scnt_e, roff_e, soff_e, eoff;
+    DevBuf roff, slen, rbeg, rpre, rcode;
+    DevBuf icount, ioff, iblock, is0;
+    DevBuf sizes;      // int64 [8]: nblock, nitem, ... read by graph-captured kernels
+    DevBuf misc;       // counters and flags
+};
 
 // ------------------------------------------------------------- launches --
 // keys_sort.hip
-int launch_keys(const double* pos, int64_t n, double L, int bits, uint64_t* keys,
-                int32_t* iota, int* bad_flag, hipStream_t s);
-int sort_workspace(int64_t n, int bits, size_t* bytes);
-int launch_sort(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out,
-                int32_t* perm_out, int64_t n, int bits, void* ws, size_t ws_bytes, hipStream_t s);
-int launch_gather(const double* pos, const float* mass_f, const double* mass_d,
-                  const int32_t* perm, int64_t n, double L, double* pos_s, float* mass_s_f,
-                  double* mass_s_d, int* bad_flag, hipStream_t s);
+int stage_keys(const BatchDev& bd, int64_t N, const double* pos, Work& w, hipStream_t s);
+int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
+int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* mass_f,
+                 const double* mass_d, Work& w, hipStream_t s);
+int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes);
 int scan_workspace(int64_t n, size_t* bytes);
+int grow_scan(DevBuf& buf, int64_t n);
 // exclusive scan of int32 counts into int64 offsets; off has n + 1 entries
-int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, void* ws, size_t ws_bytes,
-                           hipStream_t s);
+int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s);
+int launch_keys_raw(const double* pos, int64_t n, double L, int bits, uint64_t* keys,
+                    hipStream_t s);
+int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out,
+                    int32_t* perm_out, int64_t n, int bits, void* ws, size_t ws_bytes,
+                    hipStream_t s);
 
 // tree.hip
-struct LeafBuffers {           // device arrays sized for n particles
-    int8_t* lam;               // n + leaf_max
-    int8_t* pmax;              // n + leaf_max
-    int8_t* smax;              // n + leaf_max
-    int8_t* level_p;           // n  leaf level of each particle
-    int32_t* flag;             // n  leaf-start flags
-    int64_t* flag_off;         // n + 1
-};
-int build_leaves_device(const uint64_t* sorted_keys, const double* pos_s, int64_t n, const Geo& g,
-                        int leaf_max, LeafBuffers& lb, void* scan_ws, size_t scan_ws_bytes,
-                        DevBuf& begin, DevBuf& count, DevBuf& level, DevBuf& prefix, DevBuf& boxes,
-                        int64_t* nleaf_out, hipStream_t s);
-int build_tree(const IBox* leaf_boxes, int64_t nleaf, DevBuf& tree_boxes, TreeView* tv,
-               hipStream_t s);
-int build_canonical_pairs(const TreeView& tv, int64_t nleaf, const Geo& g, DevBuf& row_cnt,
-                          DevBuf& row_ptr, DevBuf& src, DevBuf& code, void* scan_ws,
-                          size_t scan_ws_bytes, int64_t* nentries, hipStream_t s);
-
-// Target blocks: runs of at most kBlock consecutive particles (key order)
-// inside one kBlock-particle chunk whose bounding box side stays within
-// r_cut (so FP32 offsets from the block centre stay small).
-constexpr int kBlock = 64;
-struct BlockLists {
-    int64_t nblock = 0, nrange = 0, nitem = 0, nchunk = 0;
-    int64_t candidates = 0;
-    DevBuf ccount;     // int32 [nchunk] blocks per chunk
-    DevBuf coff;       // int64 [nchunk + 1]
-    DevBuf bstart;     // int32 [nblock] first particle
-    DevBuf bcount;     // int32 [nblock] particles (1..kBlock)
-    DevBuf box;        // IBox [nblock]
-    int64_t nentry = 0;
-    DevBuf fent_a, fent_b;  // breadth-first entries (block, shift, node)
-    DevBuf fcnt;       // int32 per entry: children / ranges
-    DevBuf foff;       // int64 scan of fcnt
-    DevBuf lmask_e;    // uint64 [nentry] passing leaves of the entry's subtree
-    DevBuf rcnt_e;     // int32 [nentry] ranges per entry
-    DevBuf scnt_e;     // int32 [nentry] listed sources per entry
-    DevBuf roff_e;     // int64 [nentry + 1]
-    DevBuf soff_e;     // int64 [nentry + 1]
-    DevBuf eoff;       // int64 [nblock + 1] first entry of each block
-    DevBuf roff;       // int64 [nblock + 1] first range of each block
-    DevBuf rbeg;       // int32 [nrange] first source particle
-    DevBuf rpre;       // int32 [nrange] exclusive prefix of lengths in the block list
-    DevBuf rcode;      // uint8 [nrange] periodic shift code
-    DevBuf slen;       // int32 [nblock] total sources in the block list
-    DevBuf icount;     // int32 [nblock] work items per block
-    DevBuf ioff;       // int64 [nblock + 1]
-    DevBuf iblock;     // int32 [nitem]
-    DevBuf is0;        // int32 [nitem] first list position of the item
-};
-int build_block_lists(const double* pos_s, int64_t n, const int64_t* leaf_begin,
-                      const int32_t* leaf_count, const TreeView& tv, int64_t nleaf, const Geo& g,
-                      int chunk, double rcut, BlockLists& bl, DevBuf& scan_ws, hipStream_t s);
+int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
+                 Work& w, hipStream_t s);
+int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);
+int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
+                hipStream_t s);
+int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t T, DevBuf& row_cnt,
+                          DevBuf& row_ptr, DevBuf& src, DevBuf& code, DevBuf& scan_ws,
+                          int64_t* nentries, hipStream_t s);
 
 // pp_kernels.hip
-struct PolyF32 {
-    float c[10];     // K * H coefficients in t, highest last
-    float tscale;    // t = r2n * tscale - 1
-    float eps2n;     // softening^2 / rcut^2 (floored)
-    float cut2;      // 1 + eps2n
-};
-int make_poly(const pp_box_params& p, PolyF32* out);
-int launch_pp_f32(const BlockLists& bl, const double* pos_s, const float* mass_s, int64_t n,
-                  const pp_box_params& p, const PolyF32& poly, int chunk, float* partial,
-                  unsigned long long* counters, hipStream_t s);
-int launch_reduce_f32(const BlockLists& bl, const float* partial, const int32_t* perm, int64_t n,
-                      double scale, float* acc, hipStream_t s);
-int launch_pp_f64(const BlockLists& bl, const double* pos_s, const double* mass_s, int64_t n,
-                  const pp_box_params& p, int chunk, double* partial, hipStream_t s);
-int launch_reduce_f64(const BlockLists& bl, const double* partial, const int32_t* perm, int64_t n,
-                      double* acc, hipStream_t s);
-int launch_count(const BlockLists& bl, const double* pos_s, int64_t n, const pp_box_params& p,
-                 int chunk, int32_t* partial_counts, hipStream_t s);
-int launch_reduce_count(const BlockLists& bl, const int32_t* partial, const int32_t* perm,
-                        int64_t n, int64_t* counts, unsigned long long* total, hipStream_t s);
+enum class Mode { kGrid = 0, kPersistent = 1 };
+// variant bits: 1 = one Newton step after the hardware rsqrt, 2 = no Kahan
+// compensation, 4 = no FP64 block-origin subtraction (box-origin offsets)
+int launch_pp_f32(const BatchDev& bd, const Work& w, int chunk, Mode mode, int waves_per_cu,
+                  int variant, float* partial, unsigned long long* counters, unsigned* queues,
+                  hipStream_t s);
+int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,
+                      hipStream_t s);
+int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial, hipStream_t s);
+int launch_reduce_f64(const BatchDev& bd, const Work& w, const double* partial, double* acc,
+                      hipStream_t s);
+int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial, hipStream_t s);
+int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partial, int64_t* counts,
+                        unsigned long long* total, hipStream_t s);
+int launch_reset_queues(unsigned* queues, hipStream_t s);
 
 }  // namespace pp

@@ -4,10 +4,10 @@
 // Per pair (sec. 3.1, Eq. equ:split, with Plummer softening):
 //   a_i += G m_j d g(s_eps / 2 r_s) / s_eps^3,   kept iff s < r_cut.
 // FP32 form.  Lengths are in units of r_cut, relative to the FP64 centre of
-// the target block (the origin subtraction is done in FP64 when a source
-// tile is staged, so the FP32 offsets are small and precise).  With
-// r2 = s_eps^2, y = 1/s_eps (hardware reciprocal square root) and
-// u = x^2 = r2 k^2, k = r_cut / (2 r_s):
+// the target block (the origin subtraction is done in FP64 when a source is
+// staged, so the FP32 offsets are small and precise).  With r2 = s_eps^2,
+// y = 1/s_eps (hardware reciprocal square root) and u = x^2 = r2 k^2,
+// k = r_cut / (2 r_s):
 //   g / s_eps^3 = y^3 - k^3 H(u),   g(x) = 1 - x^3 H(x^2),
 // H a fitted polynomial (split_poly.h).  Softening enters r2 through the
 // first fused multiply-add; the cut test compares r2 with 1 + eps^2.
@@ -24,7 +24,43 @@
 namespace pp {
 namespace {
 
-inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+struct ItemArgs {
+    const int32_t* iblock;
+    const int32_t* is0;
+    const int64_t* sizes;      // [0] nblock, [1] nitem
+    const int32_t* bstart;
+    const int32_t* bcount;
+    const IBox* bbox;
+    const int32_t* bboxid;
+    const int64_t* roff;
+    const int32_t* rbeg;
+    const int32_t* rpre;
+    const uint8_t* rcode;
+    const int32_t* slen;
+    const int64_t* ioff;
+    const BoxDev* box;
+    int chunk;
+};
+
+ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
+    ItemArgs ia;
+    ia.iblock = w.iblock.as<int32_t>();
+    ia.is0 = w.is0.as<int32_t>();
+    ia.sizes = w.sizes.as<int64_t>();
+    ia.bstart = w.bstart.as<int32_t>();
+    ia.bcount = w.bcount.as<int32_t>();
+    ia.bbox = w.bbox.as<IBox>();
+    ia.bboxid = w.bboxid.as<int32_t>();
+    ia.roff = w.roff.as<int64_t>();
+    ia.rbeg = w.rbeg.as<int32_t>();
+    ia.rpre = w.rpre.as<int32_t>();
+    ia.rcode = w.rcode.as<uint8_t>();
+    ia.slen = w.slen.as<int32_t>();
+    ia.ioff = w.ioff.as<int64_t>();
+    ia.box = bd.box;
+    ia.chunk = w.chunk;       // the effective chunk the items were cut with
+    return ia;
+}
 
 // Items are laid out so that the 8 XCDs (which take workgroups round-robin)
 // each see one contiguous stretch of items: neighbouring target blocks share
@@ -35,29 +71,14 @@ __device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
 
 __device__ __forceinline__ int64_t find_range(const int32_t* __restrict__ rpre, int64_t lo,
                                               int64_t hi, int32_t p) {
-    // last r in [lo, hi] with rpre[r] <= p (rpre ascending, rpre[lo] = 0 <= p)
+    // last r in [lo, hi] with rpre[r] <= p (rpre ascending, rpre[lo] <= p)
     while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
+        const int64_t mid = (lo + hi + 1) >> 1;
         if (rpre[mid] <= p) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
-
-struct ItemArgs {
-    const int32_t* iblock;
-    const int32_t* is0;
-    int64_t nitem, per_xcd;
-    const int32_t* bstart;
-    const int32_t* bcount;
-    const IBox* bbox;
-    const int64_t* roff;
-    const int32_t* rbeg;
-    const int32_t* rpre;
-    const uint8_t* rcode;
-    const int32_t* slen;
-    int chunk;
-};
 
 // One source against the lane's target; adds into (tx, ty, tz).
 template <bool NEWTON>
@@ -110,31 +131,35 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// FP32 PP kernel, one wave per work item (target block, chunk of its
-// source list).  Sources are fetched 64 list positions at a time: each lane
-// maps its position to a particle through the block's ranges (no search when
-// the window lies in one range, else a binary search bounded to 64 ranges
-// from the wave's range cursor) and loads the FP64 position and the mass;
-// the loads of the next window are issued before the current tile is swept.
-// A fetched source is shifted by its periodic image, made relative to the
-// FP64 block centre, scaled by 1/r_cut and rounded to FP32, and dropped if
-// it lies at r_cut or more from the block's box.  Survivors are compacted
-// with a ballot into a 128-entry LDS ring; every 64 survivors are swept by
-// all lanes with broadcast LDS reads.
-template <bool NEWTON>
-__global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
-                                                    const float* __restrict__ mass_s, int64_t n,
-                                                    double L, double cell, double inv_rcut,
-                                                    PolyF32 P, float* __restrict__ partial,
-                                                    unsigned long long* __restrict__ counters) {
-    const int64_t item = xcd_item(blockIdx.x, ia.per_xcd);
-    if (item >= ia.nitem) return;
+// One work item of the FP32 PP kernel on one wave (target block, chunk of
+// its source list).  Sources are fetched 64 list positions at a time: each
+// lane maps its position to a particle through the block's ranges (no
+// search when the window lies in one range, else a binary search bounded to
+// 64 ranges from the wave's range cursor) and loads the FP64 position and
+// the mass; the loads of the next window are issued before the current tile
+// is swept.  A fetched source is shifted by its periodic image, made
+// relative to the FP64 block centre, scaled by 1/r_cut and rounded to FP32,
+// and dropped if it lies at r_cut or more from the block's box.  Survivors
+// are compacted with a ballot into a 128-entry LDS ring; every 64 survivors
+// are swept by all lanes with broadcast LDS reads.
+template <int VAR>
+__device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
+                                        const double* __restrict__ pos_s,
+                                        const float* __restrict__ mass_s, int64_t N,
+                                        float* __restrict__ partial,
+                                        unsigned long long* __restrict__ counters, float4* tile) {
+    constexpr bool NEWTON = (VAR & 1) != 0;
+    constexpr bool KAHAN = (VAR & 2) == 0;
+    constexpr bool LOCAL = (VAR & 4) == 0;     // FP64 block-centre subtraction
     const int lane = threadIdx.x;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
     const int32_t nt = ia.bcount[b];
+    const BoxDev& X = ia.box[ia.bboxid[b]];
+    const double L = X.L, cell = X.cell, inv_rcut = X.inv_rcut;
+    const PolyF32 P = X.poly;
     const IBox B = ia.bbox[b];
     const double ox = 0.5 * (double)(B.lo[0] + B.hi[0]) * cell;
     const double oy = 0.5 * (double)(B.lo[1] + B.hi[1]) * cell;
@@ -148,12 +173,11 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
     const int64_t t = (int64_t)ia.bstart[b] + lane;
     float xi = 0.f, yi = 0.f, zi = 0.f;
     if (lane < nt) {
-        xi = (float)((pos_s[t] - ox) * inv_rcut);
-        yi = (float)((pos_s[n + t] - oy) * inv_rcut);
-        zi = (float)((pos_s[2 * n + t] - oz) * inv_rcut);
+        xi = (float)((pos_s[t] - (LOCAL ? ox : 0.0)) * inv_rcut);
+        yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_rcut);
+        zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_rcut);
     }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
-    __shared__ float4 tile[2 * kBlock];
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     int count = 0;                                   // staged sources (wave-uniform)
     int64_t staged = 0;
@@ -176,12 +200,13 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
             const int64_t j = (int64_t)ia.rbeg[r] + (p - ia.rpre[r]);
             pc = ia.rcode[r];
             px = pos_s[j];
-            py = pos_s[n + j];
-            pz = pos_s[2 * n + j];
+            py = pos_s[N + j];
+            pz = pos_s[2 * N + j];
             pm = mass_s[j];
         }
         rcur = readlane64(r, kBlock - 1);
     };
+    wave_sync();
     if (s0 < s1) fetch(s0);
     for (int32_t base = s0; base < s1; base += kBlock) {
         bool keep = false;
@@ -198,6 +223,11 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
             const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
             const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
             keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+            if (!LOCAL) {
+                v.x = (float)((px + sx) * inv_rcut);
+                v.y = (float)((py + sy) * inv_rcut);
+                v.z = (float)((pz + sz) * inv_rcut);
+            }
         }
         const uint64_t bal = __ballot(keep);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
@@ -211,11 +241,16 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
         if (count >= kBlock) {
             wave_sync();
             float tx = 0.f, ty = 0.f, tz = 0.f;
+            if (KAHAN) {
 #pragma unroll 8
-            for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
-            kahan_add(ax, cx, tx);
-            kahan_add(ay, cy, ty);
-            kahan_add(az, cz, tz);
+                for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+                kahan_add(ax, cx, tx);
+                kahan_add(ay, cy, ty);
+                kahan_add(az, cz, tz);
+            } else {
+#pragma unroll 8
+                for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, ax, ay, az);
+            }
             wave_sync();
             count -= kBlock;
             if (lane < count) tile[lane] = tile[kBlock + lane];
@@ -225,10 +260,14 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
     if (count > 0) {
         wave_sync();
         float tx = 0.f, ty = 0.f, tz = 0.f;
-        for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
-        kahan_add(ax, cx, tx);
-        kahan_add(ay, cy, ty);
-        kahan_add(az, cz, tz);
+        if (KAHAN) {
+            for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+            kahan_add(ax, cx, tx);
+            kahan_add(ay, cy, ty);
+            kahan_add(az, cz, tz);
+        } else {
+            for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, ax, ay, az);
+        }
     }
     if (counters && lane == 0) {
         atomicAdd(counters, (unsigned long long)staged * (unsigned long long)nt);
@@ -243,31 +282,79 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
     o[5 * kBlock + lane] = cz;
 }
 
-// One thread per (block, lane): sum the item partials of the block in
-// order (FP64), scale, and scatter to input order.
-__global__ void __launch_bounds__(256) reduce_f32_kernel(const int64_t* __restrict__ ioff,
-                                                         const int32_t* __restrict__ bstart,
-                                                         const int32_t* __restrict__ bcount,
-                                                         int64_t nblock,
+// One workgroup per item.
+template <int VAR>
+__global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
+                                                    const float* __restrict__ mass_s, int64_t N,
+                                                    int64_t per_xcd, float* __restrict__ partial,
+                                                    unsigned long long* __restrict__ counters) {
+    __shared__ float4 tile[2 * kBlock];
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= ia.sizes[1]) return;
+    pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile);
+}
+
+// Persistent form: a fixed grid of waves pulls items from 8 queues (one
+// contiguous stretch of items per XCD, as above); a wave first drains the
+// queue of its own XCD, then steals from the others.  Every wave leaves
+// once all queues are empty.  The item count is read from device memory,
+// so the launch can be replayed from a graph while the lists change.
+template <int VAR>
+__global__ void __launch_bounds__(64) pp_f32_persistent(ItemArgs ia,
+                                                        const double* __restrict__ pos_s,
+                                                        const float* __restrict__ mass_s, int64_t N,
+                                                        float* __restrict__ partial,
+                                                        unsigned long long* __restrict__ counters,
+                                                        unsigned* __restrict__ queues) {
+    __shared__ float4 tile[2 * kBlock];
+    const int64_t nitem = ia.sizes[1];
+    const int64_t per = (nitem + 7) / 8;
+    const int my = blockIdx.x & 7;
+    for (int v = 0; v < 8; ++v) {
+        const int q = (my + v) & 7;
+        const int64_t qbeg = q * per;
+        const int64_t qend = qbeg + per < nitem ? qbeg + per : nitem;
+        if (qbeg >= qend) continue;
+        for (;;) {
+            unsigned i = 0;
+            if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
+            i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
+            const int64_t item = qbeg + (int64_t)i;
+            if (item >= qend) break;
+            pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile);
+        }
+    }
+}
+
+__global__ void reset_queues_kernel(unsigned* q) {
+    if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
+
+// One thread per (block, lane), grid-stride: sum the item partials of the
+// block in order (FP64), scale by G / r_cut^2, scatter to input order.
+__global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
                                                          const float* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
-                                                         int64_t n, double scale,
-                                                         float* __restrict__ acc) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t b = g / kBlock;
-    const int l = (int)(g % kBlock);
-    if (b >= nblock || l >= bcount[b]) return;
-    double sx = 0, sy = 0, sz = 0;
-    for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) {
-        const float* o = partial + it * 6 * kBlock;
-        sx += (double)o[0 * kBlock + l] - (double)o[3 * kBlock + l];
-        sy += (double)o[1 * kBlock + l] - (double)o[4 * kBlock + l];
-        sz += (double)o[2 * kBlock + l] - (double)o[5 * kBlock + l];
+                                                         int64_t N, float* __restrict__ acc) {
+    const int64_t nblock = ia.sizes[0];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nblock * kBlock;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = g / kBlock;
+        const int l = (int)(g % kBlock);
+        if (l >= ia.bcount[b]) continue;
+        double sx = 0, sy = 0, sz = 0;
+        for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) {
+            const float* o = partial + it * 6 * kBlock;
+            sx += (double)o[0 * kBlock + l] - (double)o[3 * kBlock + l];
+            sy += (double)o[1 * kBlock + l] - (double)o[4 * kBlock + l];
+            sz += (double)o[2 * kBlock + l] - (double)o[5 * kBlock + l];
+        }
+        const double scale = ia.box[ia.bboxid[b]].scale;
+        const int64_t i = perm[(int64_t)ia.bstart[b] + l];
+        acc[i] = (float)(sx * scale);
+        acc[N + i] = (float)(sy * scale);
+        acc[2 * N + i] = (float)(sz * scale);
     }
-    const int64_t i = perm[(int64_t)bstart[b] + l];
-    acc[i] = (float)(sx * scale);
-    acc[n + i] = (float)(sy * scale);
-    acc[2 * n + i] = (float)(sz * scale);
 }
 
 // ------------------------------------------------------------------ FP64 --
@@ -279,24 +366,25 @@ __device__ __forceinline__ double split_factor_f64(double x) {
 
 template <bool COUNT>
 __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* __restrict__ pos_s,
-                                                    const double* __restrict__ mass_s, int64_t n,
-                                                    double L, double rs, double rcut, double eps,
-                                                    double G, double* __restrict__ partial,
+                                                    const double* __restrict__ mass_s, int64_t N,
+                                                    int64_t per_xcd, double* __restrict__ partial,
                                                     int32_t* __restrict__ pcount) {
-    const int64_t item = xcd_item(blockIdx.x, ia.per_xcd);
-    if (item >= ia.nitem) return;
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= ia.sizes[1]) return;
     const int lane = threadIdx.x;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
+    const BoxDev& X = ia.box[ia.bboxid[b]];
+    const double L = X.L, rs = X.rs, rcut = X.rcut, eps = X.eps, G = X.G;
     const bool active = lane < ia.bcount[b];
     const int64_t t = active ? (int64_t)ia.bstart[b] + lane : -2;
     double xi = 0, yi = 0, zi = 0;
     if (active) {
         xi = pos_s[t];
-        yi = pos_s[n + t];
-        zi = pos_s[2 * n + t];
+        yi = pos_s[N + t];
+        zi = pos_s[2 * N + t];
     }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
     __shared__ double4 tile[kBlock];
@@ -315,8 +403,8 @@ __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* _
             j = (int64_t)ia.rbeg[r] + (p - ia.rpre[r]);
             c = ia.rcode[r];
             v.x = pos_s[j];
-            v.y = pos_s[n + j];
-            v.z = pos_s[2 * n + j];
+            v.y = pos_s[N + j];
+            v.z = pos_s[2 * N + j];
             v.w = COUNT ? 0.0 : mass_s[j];
         }
         __syncthreads();
@@ -359,64 +447,42 @@ __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* _
 }
 #pragma clang fp contract(on)
 
-__global__ void __launch_bounds__(256) reduce_f64_kernel(const int64_t* __restrict__ ioff,
-                                                         const int32_t* __restrict__ bstart,
-                                                         const int32_t* __restrict__ bcount,
-                                                         int64_t nblock,
+__global__ void __launch_bounds__(256) reduce_f64_kernel(ItemArgs ia,
                                                          const double* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
-                                                         int64_t n, double* __restrict__ acc) {
+                                                         int64_t N, double* __restrict__ acc) {
+    const int64_t nblock = ia.sizes[0];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = g / kBlock;
     const int l = (int)(g % kBlock);
-    if (b >= nblock || l >= bcount[b]) return;
+    if (b >= nblock || l >= ia.bcount[b]) return;
     double sx = 0, sy = 0, sz = 0;
-    for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) {
+    for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) {
         const double* o = partial + it * 3 * kBlock;
         sx += o[0 * kBlock + l];
         sy += o[1 * kBlock + l];
         sz += o[2 * kBlock + l];
     }
-    const int64_t i = perm[(int64_t)bstart[b] + l];
+    const int64_t i = perm[(int64_t)ia.bstart[b] + l];
     acc[i] = sx;
-    acc[n + i] = sy;
-    acc[2 * n + i] = sz;
+    acc[N + i] = sy;
+    acc[2 * N + i] = sz;
 }
 
-__global__ void __launch_bounds__(256) reduce_count_kernel(const int64_t* __restrict__ ioff,
-                                                           const int32_t* __restrict__ bstart,
-                                                           const int32_t* __restrict__ bcount,
-                                                           int64_t nblock,
+__global__ void __launch_bounds__(256) reduce_count_kernel(ItemArgs ia,
                                                            const int32_t* __restrict__ pc,
                                                            const int32_t* __restrict__ perm,
-                                                           int64_t n, int64_t* __restrict__ counts,
+                                                           int64_t* __restrict__ counts,
                                                            unsigned long long* __restrict__ total) {
+    const int64_t nblock = ia.sizes[0];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = g / kBlock;
     const int l = (int)(g % kBlock);
-    if (b >= nblock || l >= bcount[b]) return;
+    if (b >= nblock || l >= ia.bcount[b]) return;
     int64_t s = 0;
-    for (int64_t it = ioff[b]; it < ioff[b + 1]; ++it) s += pc[it * kBlock + l];
-    if (counts) counts[perm[(int64_t)bstart[b] + l]] = s;
+    for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) s += pc[it * kBlock + l];
+    if (counts) counts[perm[(int64_t)ia.bstart[b] + l]] = s;
     atomicAdd(total, (unsigned long long)s);
-}
-
-ItemArgs item_args(const BlockLists& bl, int chunk) {
-    ItemArgs ia;
-    ia.iblock = bl.iblock.as<int32_t>();
-    ia.is0 = bl.is0.as<int32_t>();
-    ia.nitem = bl.nitem;
-    ia.per_xcd = (bl.nitem + 7) / 8;
-    ia.bstart = bl.bstart.as<int32_t>();
-    ia.bcount = bl.bcount.as<int32_t>();
-    ia.bbox = bl.box.as<IBox>();
-    ia.roff = bl.roff.as<int64_t>();
-    ia.rbeg = bl.rbeg.as<int32_t>();
-    ia.rpre = bl.rpre.as<int32_t>();
-    ia.rcode = bl.rcode.as<uint8_t>();
-    ia.slen = bl.slen.as<int32_t>();
-    ia.chunk = chunk;
-    return ia;
 }
 
 }  // namespace
@@ -431,69 +497,103 @@ int make_poly(const pp_box_params& p, PolyF32* out) {
     if (e2 < floor2) e2 = floor2;
     out->eps2n = (float)e2;
     out->cut2 = (float)(1.0 + e2);
+    out->pad = 0.f;
     return PP_OK;
 }
 
-int launch_pp_f32(const BlockLists& bl, const double* pos_s, const float* mass_s, int64_t n,
-                  const pp_box_params& p, const PolyF32& poly, int chunk, float* partial,
-                  unsigned long long* counters, hipStream_t s) {
-    if (bl.nitem == 0) return PP_OK;
-    ItemArgs ia = item_args(bl, chunk);
-    const double cell = p.L / (double)(1ll << p.key_bits);
-    hipLaunchKernelGGL(pp_f32_kernel<false>, dim3((unsigned)(ia.per_xcd * 8)), dim3(kBlock), 0, s,
-                       ia, pos_s, mass_s, n, p.L, cell, 1.0 / p.rcut, poly, partial, counters);
+int launch_reset_queues(unsigned* queues, hipStream_t s) {
+    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, queues);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_reduce_f32(const BlockLists& bl, const float* partial, const int32_t* perm, int64_t n,
-                      double scale, float* acc, hipStream_t s) {
-    if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_f32_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
-                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
-                       bl.nblock, partial, perm, n, scale, acc);
+template <int VAR>
+static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int waves_per_cu,
+                             float* partial, unsigned long long* counters, unsigned* queues,
+                             hipStream_t s) {
+    if (mode == Mode::kPersistent) {
+        int dev = 0, cus = 256;
+        PP_HIP(hipGetDevice(&dev));
+        PP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const unsigned grid = (unsigned)(cus * (waves_per_cu > 0 ? waves_per_cu : 16));
+        hipLaunchKernelGGL(pp_f32_persistent<VAR>, dim3(grid), dim3(kBlock), 0, s, ia,
+                           w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters,
+                           queues);
+    } else {
+        if (w.nitem == 0) return PP_OK;
+        const int64_t per = (w.nitem + 7) / 8;
+        hipLaunchKernelGGL(pp_f32_kernel<VAR>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
+                           w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, per, partial,
+                           counters);
+    }
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_pp_f64(const BlockLists& bl, const double* pos_s, const double* mass_s, int64_t n,
-                  const pp_box_params& p, int chunk, double* partial, hipStream_t s) {
-    if (bl.nitem == 0) return PP_OK;
-    ItemArgs ia = item_args(bl, chunk);
-    hipLaunchKernelGGL(pp_f64_kernel<false>, dim3((unsigned)(ia.per_xcd * 8)), dim3(kBlock), 0, s,
-                       ia, pos_s, mass_s, n, p.L, p.rs, p.rcut, p.eps, p.G, partial,
+int launch_pp_f32(const BatchDev& bd, const Work& w, int chunk, Mode mode, int waves_per_cu,
+                  int variant, float* partial, unsigned long long* counters, unsigned* queues,
+                  hipStream_t s) {
+    const ItemArgs ia = item_args(bd, w, chunk);
+    switch (variant & 7) {
+        case 0: return launch_pp_f32_var<0>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 1: return launch_pp_f32_var<1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 2: return launch_pp_f32_var<2>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 3: return launch_pp_f32_var<3>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 4: return launch_pp_f32_var<4>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 5: return launch_pp_f32_var<5>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 6: return launch_pp_f32_var<6>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        default: return launch_pp_f32_var<7>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+    }
+}
+
+int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,
+                      hipStream_t s) {
+    ItemArgs ia = item_args(bd, w, 0);
+    // a fixed grid (grid-stride) so a captured graph stays valid as nblock changes
+    hipLaunchKernelGGL(reduce_f32_kernel, dim3(2048), dim3(256), 0, s, ia, partial,
+                       w.perm.as<int32_t>(), w.pos_n, acc);
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
+int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial, hipStream_t s) {
+    if (w.nitem == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w, chunk);
+    const int64_t per = (w.nitem + 7) / 8;
+    hipLaunchKernelGGL(pp_f64_kernel<false>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
+                       w.pos_s.as<double>(), w.mass_sd.as<double>(), w.pos_n, per, partial,
                        (int32_t*)nullptr);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_reduce_f64(const BlockLists& bl, const double* partial, const int32_t* perm, int64_t n,
-                      double* acc, hipStream_t s) {
-    if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
-                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
-                       bl.nblock, partial, perm, n, acc);
+int launch_reduce_f64(const BatchDev& bd, const Work& w, const double* partial, double* acc,
+                      hipStream_t s) {
+    if (w.nblock == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w, 0);
+    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(w.nblock * kBlock, 256)), dim3(256), 0, s,
+                       ia, partial, w.perm.as<int32_t>(), w.pos_n, acc);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_count(const BlockLists& bl, const double* pos_s, int64_t n, const pp_box_params& p,
-                 int chunk, int32_t* partial_counts, hipStream_t s) {
-    if (bl.nitem == 0) return PP_OK;
-    ItemArgs ia = item_args(bl, chunk);
-    hipLaunchKernelGGL(pp_f64_kernel<true>, dim3((unsigned)(ia.per_xcd * 8)), dim3(kBlock), 0, s,
-                       ia, pos_s, (const double*)nullptr, n, p.L, p.rs, p.rcut, p.eps, p.G,
-                       (double*)nullptr, partial_counts);
+int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial, hipStream_t s) {
+    if (w.nitem == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w, chunk);
+    const int64_t per = (w.nitem + 7) / 8;
+    hipLaunchKernelGGL(pp_f64_kernel<true>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
+                       w.pos_s.as<double>(), (const double*)nullptr, w.pos_n, per,
+                       (double*)nullptr, partial);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_reduce_count(const BlockLists& bl, const int32_t* partial, const int32_t* perm,
-                        int64_t n, int64_t* counts, unsigned long long* total, hipStream_t s) {
-    if (n == 0) return PP_OK;
-    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(bl.nblock * kBlock, 256)), dim3(256), 0,
-                       s, bl.ioff.as<int64_t>(), bl.bstart.as<int32_t>(), bl.bcount.as<int32_t>(),
-                       bl.nblock, partial, perm, n, counts, total);
+int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partial, int64_t* counts,
+                        unsigned long long* total, hipStream_t s) {
+    if (w.nblock == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w, 0);
+    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(w.nblock * kBlock, 256)), dim3(256), 0,
+                       s, ia, partial, w.perm.as<int32_t>(), counts, total);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }

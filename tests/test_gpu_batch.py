@@ -1,0 +1,124 @@
+"""GPU tests of the batched form (many boxes, one persistent work-stealing
+launch replayed from a hipGraph) and of the launch-shape options.
+
+The batched path must give, box by box, bit-identical accelerations to one
+plain pp_accel per box (same lists, same work items, fixed-order
+reductions), must match the FP64 oracle to the same tolerances, and graph
+replays must repeat the eager result exactly, with other GPU work between
+the replays.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import BoxParams
+from tests import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_09824_amd as m
+    return m
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def small_batch(nbox=7, seed=5):
+    rng = np.random.default_rng(seed)
+    boxes = []
+    for b in range(nbox):
+        n = int(rng.integers(1, 6000)) if b != 3 else 1
+        L = float(rng.uniform(20.0, 80.0))
+        frac = float(rng.uniform(0.0, 0.8))
+        n_mesh = max(12, int(round(n ** (1 / 3))))
+        pos = W.mixture(rng, n, L, frac, max(1, n // 500))
+        boxes.append(W.Box(pos=pos, mass=rng.uniform(0.5, 1.5, n).astype(np.float32),
+                           params=BoxParams.from_mesh(L, n_mesh), name=f"b{b}"))
+    return boxes
+
+
+def concat(boxes):
+    pos = np.concatenate([b.pos for b in boxes], axis=1)
+    mass = np.concatenate([b.mass for b in boxes])
+    return pos, mass
+
+
+def test_batch_bit_identical_to_per_box(pp):
+    boxes = small_batch()
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    acc = bp.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    off = 0
+    for b in boxes:
+        plan = pp.Plan(b.params, b.n)
+        a1 = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()
+        assert np.array_equal(acc[:, off:off + b.n], a1), b.name
+        off += b.n
+
+
+def test_batch_vs_oracle(pp, oracle_mod):
+    boxes = small_batch(5, seed=11)
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    acc = bp.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    tot, counts = bp.count_interactions(per_target=True)
+    off = 0
+    n_inter = 0
+    for b in boxes:
+        ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params)
+        s = parity.summary(acc[:, off:off + b.n], ref)
+        assert s["zero_ok"] and s["median"] <= 1e-6 and s["p999"] <= 1e-4, (b.name, s)
+        assert np.array_equal(counts.cpu().numpy()[off:off + b.n], ref["n_inter"]), b.name
+        n_inter += int(ref["n_inter"].sum())
+        off += b.n
+    assert tot == n_inter
+
+
+def test_graph_replays_repeat_eager(pp):
+    boxes = small_batch(6, seed=3)
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    p, m = dev(pos, torch.float64), dev(mass, torch.float32)
+    bp.set_tuning(use_graph=0)
+    eager = bp.accel(p, m).cpu().numpy()
+    bp.set_tuning(use_graph=1)
+    out = torch.empty((3, bp.N), dtype=torch.float32, device="cuda")
+    for r in range(4):
+        out.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda").sum()      # unrelated eager work between replays
+        bp.accel(p, m, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), r
+        assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("tuning", [dict(persistent=1, waves_per_cu=4), dict(chunk=256),
+                                    dict(chunk=64, persistent=1, waves_per_cu=1),
+                                    dict(persistent=1, use_graph=1, waves_per_cu=32)])
+def test_launch_shapes_agree(pp, tuning):
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    p, m = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
+    base = plan.accel(p, m).cpu().numpy()
+    plan.set_tuning(**tuning)
+    got = plan.accel(p, m).cpu().numpy()
+    if "chunk" in tuning:
+        # a different chunk changes the work items and so the summation order
+        assert np.allclose(got, base, rtol=1e-5, atol=1e-6 * np.abs(base).max())
+    else:
+        assert np.array_equal(got, base)
+
+
+def test_tuning_validation(pp):
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    for bad in [dict(chunk=100), dict(chunk=0), dict(waves_per_cu=0), dict(use_graph=1, persistent=0)]:
+        with pytest.raises(pp.PPError):
+            plan.set_tuning(**{**dict(chunk=4096, persistent=0, waves_per_cu=16, use_graph=0), **bad})
