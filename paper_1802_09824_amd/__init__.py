@@ -38,7 +38,7 @@ class pp_box_params(C.Structure):
 
 class pp_tuning(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("use_graph", C.c_int32), ("variant", C.c_int32)]
+                ("use_graph", C.c_int32), ("variant", C.c_int32), ("groups", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -110,7 +110,7 @@ struct Batch {
     DevBuf box_dev, poff_dev;
     BatchDev bd{};
     Work w;
-    pp_tuning tune{4096, 0, 16, 0, 0};
+    pp_tuning tune{4096, 0, 16, 0, 0, 4};
     int graph_variant = -1;
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
@@ -214,7 +214,7 @@ struct Batch {
         PP_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), s));
         if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
         if (timing) PP_HIP(hipEventRecord(ev0, s));
-        PP_TRY(launch_pp_f32(bd, w, tune.chunk, tune.persistent ? Mode::kPersistent : Mode::kGrid,
+        PP_TRY(launch_pp_f32(bd, w, tune.groups, tune.persistent ? Mode::kPersistent : Mode::kGrid,
                              tune.waves_per_cu, tune.variant, partial.as<float>(), ctr,
                              queues.as<unsigned>(), s));
         if (timing) {
@@ -242,7 +242,7 @@ struct Batch {
         PP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = launch_reset_queues(queues.as<unsigned>(), s);
         if (rc == PP_OK)
-            rc = launch_pp_f32(bd, w, tune.chunk, Mode::kPersistent, tune.waves_per_cu, tune.variant,
+            rc = launch_pp_f32(bd, w, tune.groups, Mode::kPersistent, tune.waves_per_cu, tune.variant,
                                partial.as<float>(), nullptr, queues.as<unsigned>(), s);
         if (rc == PP_OK) rc = launch_reduce_f32(bd, w, partial.as<float>(), acc, s);
         hipError_t e = hipStreamEndCapture(s, &graph);
@@ -251,7 +251,7 @@ struct Batch {
         PP_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         graph_gen = alloc_generation();
         graph_acc = acc;
-        graph_variant = tune.variant;
+        graph_variant = tune.variant * 16 + tune.groups * 256 + tune.waves_per_cu;
         return PP_OK;
     }
 
@@ -259,7 +259,7 @@ struct Batch {
         PP_TRY(partial.reserve(sizeof(float) * 6 * kBlock * (w.nitem + 1)));
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
-                graph_variant != tune.variant)
+                graph_variant != tune.variant * 16 + tune.groups * 256 + tune.waves_per_cu)
                 PP_TRY(capture(acc));
             if (timing) PP_HIP(hipEventRecord(ev0, s));
             PP_HIP(hipGraphLaunch(gexec, s));
@@ -341,7 +341,8 @@ struct Batch {
                 std::string k;
                 pp_tuning t{};
                 t.variant = tune.variant;
-                if (ls >> k >> t.chunk >> t.persistent >> t.waves_per_cu >> t.use_graph && k == key &&
+                if (ls >> k >> t.chunk >> t.persistent >> t.waves_per_cu >> t.use_graph >> t.groups &&
+                    k == key &&
                     check_tuning_ok(t)) {
                     tune = t;
                     lists_valid = false;
@@ -357,7 +358,8 @@ struct Batch {
         float best_ms = 1e30f;
         for (int c : chunks) {
             for (const Shape& sh : shapes) {
-                pp_tuning t{c, sh.persistent, sh.waves, sh.persistent && batch ? 1 : 0, tune.variant};
+                pp_tuning t{c, sh.persistent, sh.waves, sh.persistent && batch ? 1 : 0, tune.variant,
+                            tune.groups};
                 tune = t;
                 float ms = 0.f;
                 PP_TRY(time_pp(pos, mass, acc, 3, s, &ms));
@@ -381,7 +383,7 @@ struct Batch {
             if (!out) return fail(PP_EINVAL, std::string("cannot write tuning cache ") + cache_path);
             for (const std::string& l : keep) out << l << "\n";
             out << key << " " << best.chunk << " " << best.persistent << " " << best.waves_per_cu
-                << " " << best.use_graph << "\n";
+                << " " << best.use_graph << " " << best.groups << "\n";
         }
         return PP_OK;
     }
@@ -389,7 +391,7 @@ struct Batch {
     static bool check_tuning_ok(const pp_tuning& t) {
         return t.chunk >= 64 && t.chunk <= (1 << 24) && t.chunk % 64 == 0 && t.waves_per_cu >= 1 &&
                t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
-               t.variant <= 7;
+               t.variant <= 7 && (t.groups == 1 || t.groups == 2 || t.groups == 4);
     }
 
     int set_timing(int on) {
@@ -410,6 +412,7 @@ static int check_tuning(const pp_tuning* t) {
     if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
     if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
     if (t->variant < 0 || t->variant > 7) return fail(PP_EINVAL, "variant must be in 0..7");
+    if (t->groups != 1 && t->groups != 2 && t->groups != 4) return fail(PP_EINVAL, "groups must be 1, 2 or 4");
     return PP_OK;
 }
 

@@ -187,7 +187,7 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
 enum class Mode { kGrid = 0, kPersistent = 1 };
 // variant bits: 1 = one Newton step after the hardware rsqrt, 2 = no Kahan
 // compensation, 4 = no FP64 block-origin subtraction (box-origin offsets)
-int launch_pp_f32(const BatchDev& bd, const Work& w, int chunk, Mode mode, int waves_per_cu,
+int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int waves_per_cu,
                   int variant, float* partial, unsigned long long* counters, unsigned* queues,
                   hipStream_t s);
 int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,

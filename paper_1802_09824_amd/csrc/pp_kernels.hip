@@ -40,6 +40,7 @@ struct ItemArgs {
     const int64_t* ioff;
     const BoxDev* box;
     int chunk;
+    int groups;                // target groups whose boxes prune the sources (1, 2 or 4)
 };
 
 ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
@@ -59,6 +60,7 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.ioff = w.ioff.as<int64_t>();
     ia.box = bd.box;
     ia.chunk = w.chunk;       // the effective chunk the items were cut with
+    ia.groups = 4;
     return ia;
 }
 
@@ -125,6 +127,10 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
@@ -177,6 +183,46 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_rcut);
         zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_rcut);
     }
+    // Boxes of the target groups (64 / groups consecutive lanes each) in the
+    // block-centre frame: a source is staged only if it lies within r_cut
+    // (with a small slack) of at least one of them.
+    float gcx[4], gcy[4], gcz[4], ghx[4], ghy[4], ghz[4];
+    const int groups = ia.groups;
+    {
+        const float bx = LOCAL ? xi : (float)((pos_s[t < N ? t : 0] - ox) * inv_rcut);
+        const float by = LOCAL ? yi : (float)((pos_s[N + (t < N ? t : 0)] - oy) * inv_rcut);
+        const float bz = LOCAL ? zi : (float)((pos_s[2 * N + (t < N ? t : 0)] - oz) * inv_rcut);
+        const bool act = lane < nt;
+        float lx = act ? bx : 3.0e38f, ly = act ? by : 3.0e38f, lz = act ? bz : 3.0e38f;
+        float ux = act ? bx : -3.0e38f, uy = act ? by : -3.0e38f, uz = act ? bz : -3.0e38f;
+        const int width = kBlock / groups;
+        for (int off = width >> 1; off > 0; off >>= 1) {
+            lx = fminf(lx, __shfl_xor(lx, off));
+            ly = fminf(ly, __shfl_xor(ly, off));
+            lz = fminf(lz, __shfl_xor(lz, off));
+            ux = fmaxf(ux, __shfl_xor(ux, off));
+            uy = fmaxf(uy, __shfl_xor(uy, off));
+            uz = fmaxf(uz, __shfl_xor(uz, off));
+        }
+        // centre and half side of the lane's group box (vector registers),
+        // then one scalar copy per group
+        const bool empty = lx > ux;
+        const float vcx = empty ? 0.f : 0.5f * (lx + ux);
+        const float vcy = empty ? 0.f : 0.5f * (ly + uy);
+        const float vcz = empty ? 0.f : 0.5f * (lz + uz);
+        const float vhx = empty ? -1.0e30f : 0.5f * (ux - lx) * 1.0001f + 1e-6f;
+        const float vhy = empty ? -1.0e30f : 0.5f * (uy - ly) * 1.0001f + 1e-6f;
+        const float vhz = empty ? -1.0e30f : 0.5f * (uz - lz) * 1.0001f + 1e-6f;
+        for (int g = 0; g < 4; ++g) {
+            const int src = g < groups ? g * width : 0;
+            gcx[g] = readlane_f(vcx, src);
+            gcy[g] = readlane_f(vcy, src);
+            gcz[g] = readlane_f(vcz, src);
+            ghx[g] = g < groups ? readlane_f(vhx, src) : -1.0e30f;
+            ghy[g] = g < groups ? readlane_f(vhy, src) : -1.0e30f;
+            ghz[g] = g < groups ? readlane_f(vhz, src) : -1.0e30f;
+        }
+    }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     int count = 0;                                   // staged sources (wave-uniform)
@@ -219,10 +265,20 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             v.y = (float)((py + sy - oy) * inv_rcut);
             v.z = (float)((pz + sz - oz) * inv_rcut);
             v.w = pm;
-            const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
-            const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
-            const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
-            keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+            if (groups <= 1) {
+                const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
+                const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
+                const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
+                keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+            } else {
+                for (int g = 0; g < 4; ++g) {
+                    if (g >= groups) break;
+                    const float gx = fmaxf(fabsf(v.x - gcx[g]) - ghx[g], 0.f);
+                    const float gy = fmaxf(fabsf(v.y - gcy[g]) - ghy[g], 0.f);
+                    const float gz = fmaxf(fabsf(v.z - gcz[g]) - ghz[g], 0.f);
+                    keep |= fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+                }
+            }
             if (!LOCAL) {
                 v.x = (float)((px + sx) * inv_rcut);
                 v.y = (float)((py + sy) * inv_rcut);
@@ -530,10 +586,11 @@ static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int w
     return PP_OK;
 }
 
-int launch_pp_f32(const BatchDev& bd, const Work& w, int chunk, Mode mode, int waves_per_cu,
+int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int waves_per_cu,
                   int variant, float* partial, unsigned long long* counters, unsigned* queues,
                   hipStream_t s) {
-    const ItemArgs ia = item_args(bd, w, chunk);
+    ItemArgs ia = item_args(bd, w, 0);
+    ia.groups = groups;
     switch (variant & 7) {
         case 0: return launch_pp_f32_var<0>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 1: return launch_pp_f32_var<1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);

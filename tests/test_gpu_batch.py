@@ -122,3 +122,32 @@ def test_tuning_validation(pp):
     for bad in [dict(chunk=100), dict(chunk=0), dict(waves_per_cu=0), dict(use_graph=1, persistent=0)]:
         with pytest.raises(pp.PPError):
             plan.set_tuning(**{**dict(chunk=4096, persistent=0, waves_per_cu=16, use_graph=0), **bad})
+
+
+def test_autotune_and_cache(pp, tmp_path):
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    p, m = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
+    base = plan.accel(p, m).cpu().numpy()
+    cache = str(tmp_path / "tune.txt")
+    t = plan.autotune(p, m, cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1] == str(t["chunk"])
+    plan2 = pp.Plan(b.params, b.n)
+    t2 = plan2.autotune(p, m, cache)           # served from the cache
+    assert t2 == t
+    got = plan2.accel(p, m).cpu().numpy()
+    assert np.allclose(got, base, rtol=1e-5, atol=1e-6 * np.abs(base).max())
+
+
+@pytest.mark.parametrize("variant", [1, 2, 4, 6])
+def test_variants_run_and_stay_close(pp, oracle_mod, variant):
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    plan.set_tuning(variant=variant)
+    acc = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()
+    ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params)
+    s = parity.summary(acc, ref)
+    assert s["zero_ok"] and s["p999"] <= 1e-3, (variant, s)
+    if variant in (1, 2):
+        assert s["median"] <= 1e-6, (variant, s)
