@@ -189,13 +189,11 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *               compensation of the per-target sums, 4 = offsets from the
  *               box origin instead of the FP64 block centre.  0 is the
  *               production kernel.
- *  groups       1, 2 or 4: a source is staged only if it lies within r_cut
- *               of the bounding box of at least one of this many groups of
- *               consecutive targets of the block (finer boxes prune more
- *               sources, at a few extra instructions per staged source).
+ *  groups       reserved, must be 1 (sources are pruned against the
+ *               target block's bounding box).
  * The chunk grows by itself when the lists are long enough that more than
  * 2^21 work items would be needed.
- * Defaults: plans {4096, 0, 16, 0, 0, 4}; batch plans {4096, 1, 16, 1, 0, 4}. */
+ * Defaults: plans {2048, 1, 16, 0, 0, 1}; batch plans {2048, 1, 16, 1, 0, 1}. */
 typedef struct pp_tuning {
     int32_t chunk, persistent, waves_per_cu, use_graph, variant, groups;
 } pp_tuning;

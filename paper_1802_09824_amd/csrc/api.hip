@@ -110,7 +110,7 @@ struct Batch {
     DevBuf box_dev, poff_dev;
     BatchDev bd{};
     Work w;
-    pp_tuning tune{4096, 0, 16, 0, 0, 4};
+    pp_tuning tune{2048, 1, 16, 0, 0, 1};
     int graph_variant = -1;
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
@@ -215,7 +215,7 @@ struct Batch {
         if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
         if (timing) PP_HIP(hipEventRecord(ev0, s));
         PP_TRY(launch_pp_f32(bd, w, tune.groups, tune.persistent ? Mode::kPersistent : Mode::kGrid,
-                             tune.waves_per_cu, tune.variant, partial.as<float>(), ctr,
+                             tune.waves_per_cu, tune.variant, partial.as<float>(), acc, ctr,
                              queues.as<unsigned>(), s));
         if (timing) {
             PP_HIP(hipEventRecord(ev1, s));
@@ -243,7 +243,7 @@ struct Batch {
         int rc = launch_reset_queues(queues.as<unsigned>(), s);
         if (rc == PP_OK)
             rc = launch_pp_f32(bd, w, tune.groups, Mode::kPersistent, tune.waves_per_cu, tune.variant,
-                               partial.as<float>(), nullptr, queues.as<unsigned>(), s);
+                               partial.as<float>(), acc, nullptr, queues.as<unsigned>(), s);
         if (rc == PP_OK) rc = launch_reduce_f32(bd, w, partial.as<float>(), acc, s);
         hipError_t e = hipStreamEndCapture(s, &graph);
         if (rc != PP_OK) return rc;
@@ -391,7 +391,7 @@ struct Batch {
     static bool check_tuning_ok(const pp_tuning& t) {
         return t.chunk >= 64 && t.chunk <= (1 << 24) && t.chunk % 64 == 0 && t.waves_per_cu >= 1 &&
                t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
-               t.variant <= 7 && (t.groups == 1 || t.groups == 2 || t.groups == 4);
+               t.variant <= 7 && t.groups == 1;
     }
 
     int set_timing(int on) {
@@ -412,7 +412,7 @@ static int check_tuning(const pp_tuning* t) {
     if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
     if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
     if (t->variant < 0 || t->variant > 7) return fail(PP_EINVAL, "variant must be in 0..7");
-    if (t->groups != 1 && t->groups != 2 && t->groups != 4) return fail(PP_EINVAL, "groups must be 1, 2 or 4");
+    if (t->groups != 1) return fail(PP_EINVAL, "groups must be 1");
     return PP_OK;
 }
 

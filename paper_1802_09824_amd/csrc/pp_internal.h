@@ -187,9 +187,11 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
 enum class Mode { kGrid = 0, kPersistent = 1 };
 // variant bits: 1 = one Newton step after the hardware rsqrt, 2 = no Kahan
 // compensation, 4 = no FP64 block-origin subtraction (box-origin offsets)
+// Blocks with a single work item write acc directly; the reduction finishes
+// the others.
 int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int waves_per_cu,
-                  int variant, float* partial, unsigned long long* counters, unsigned* queues,
-                  hipStream_t s);
+                  int variant, float* partial, float* acc, unsigned long long* counters,
+                  unsigned* queues, hipStream_t s);
 int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,
                       hipStream_t s);
 int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial, hipStream_t s);

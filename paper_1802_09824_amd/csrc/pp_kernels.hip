@@ -39,8 +39,9 @@ struct ItemArgs {
     const int32_t* slen;
     const int64_t* ioff;
     const BoxDev* box;
+    const int32_t* perm;       // key order -> input order
+    float* acc;                // FP32 output (single-item blocks write it directly)
     int chunk;
-    int groups;                // target groups whose boxes prune the sources (1, 2 or 4)
 };
 
 ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
@@ -59,8 +60,9 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.slen = w.slen.as<int32_t>();
     ia.ioff = w.ioff.as<int64_t>();
     ia.box = bd.box;
+    ia.perm = w.perm.as<int32_t>();
+    ia.acc = nullptr;
     ia.chunk = w.chunk;       // the effective chunk the items were cut with
-    ia.groups = 4;
     return ia;
 }
 
@@ -183,46 +185,6 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_rcut);
         zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_rcut);
     }
-    // Boxes of the target groups (64 / groups consecutive lanes each) in the
-    // block-centre frame: a source is staged only if it lies within r_cut
-    // (with a small slack) of at least one of them.
-    float gcx[4], gcy[4], gcz[4], ghx[4], ghy[4], ghz[4];
-    const int groups = ia.groups;
-    {
-        const float bx = LOCAL ? xi : (float)((pos_s[t < N ? t : 0] - ox) * inv_rcut);
-        const float by = LOCAL ? yi : (float)((pos_s[N + (t < N ? t : 0)] - oy) * inv_rcut);
-        const float bz = LOCAL ? zi : (float)((pos_s[2 * N + (t < N ? t : 0)] - oz) * inv_rcut);
-        const bool act = lane < nt;
-        float lx = act ? bx : 3.0e38f, ly = act ? by : 3.0e38f, lz = act ? bz : 3.0e38f;
-        float ux = act ? bx : -3.0e38f, uy = act ? by : -3.0e38f, uz = act ? bz : -3.0e38f;
-        const int width = kBlock / groups;
-        for (int off = width >> 1; off > 0; off >>= 1) {
-            lx = fminf(lx, __shfl_xor(lx, off));
-            ly = fminf(ly, __shfl_xor(ly, off));
-            lz = fminf(lz, __shfl_xor(lz, off));
-            ux = fmaxf(ux, __shfl_xor(ux, off));
-            uy = fmaxf(uy, __shfl_xor(uy, off));
-            uz = fmaxf(uz, __shfl_xor(uz, off));
-        }
-        // centre and half side of the lane's group box (vector registers),
-        // then one scalar copy per group
-        const bool empty = lx > ux;
-        const float vcx = empty ? 0.f : 0.5f * (lx + ux);
-        const float vcy = empty ? 0.f : 0.5f * (ly + uy);
-        const float vcz = empty ? 0.f : 0.5f * (lz + uz);
-        const float vhx = empty ? -1.0e30f : 0.5f * (ux - lx) * 1.0001f + 1e-6f;
-        const float vhy = empty ? -1.0e30f : 0.5f * (uy - ly) * 1.0001f + 1e-6f;
-        const float vhz = empty ? -1.0e30f : 0.5f * (uz - lz) * 1.0001f + 1e-6f;
-        for (int g = 0; g < 4; ++g) {
-            const int src = g < groups ? g * width : 0;
-            gcx[g] = readlane_f(vcx, src);
-            gcy[g] = readlane_f(vcy, src);
-            gcz[g] = readlane_f(vcz, src);
-            ghx[g] = g < groups ? readlane_f(vhx, src) : -1.0e30f;
-            ghy[g] = g < groups ? readlane_f(vhy, src) : -1.0e30f;
-            ghz[g] = g < groups ? readlane_f(vhz, src) : -1.0e30f;
-        }
-    }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     int count = 0;                                   // staged sources (wave-uniform)
@@ -265,20 +227,10 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             v.y = (float)((py + sy - oy) * inv_rcut);
             v.z = (float)((pz + sz - oz) * inv_rcut);
             v.w = pm;
-            if (groups <= 1) {
-                const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
-                const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
-                const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
-                keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
-            } else {
-                for (int g = 0; g < 4; ++g) {
-                    if (g >= groups) break;
-                    const float gx = fmaxf(fabsf(v.x - gcx[g]) - ghx[g], 0.f);
-                    const float gy = fmaxf(fabsf(v.y - gcy[g]) - ghy[g], 0.f);
-                    const float gz = fmaxf(fabsf(v.z - gcz[g]) - ghz[g], 0.f);
-                    keep |= fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
-                }
-            }
+            const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
+            const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
+            const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
+            keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
             if (!LOCAL) {
                 v.x = (float)((px + sx) * inv_rcut);
                 v.y = (float)((py + sy) * inv_rcut);
@@ -328,6 +280,16 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     if (counters && lane == 0) {
         atomicAdd(counters, (unsigned long long)staged * (unsigned long long)nt);
         atomicAdd(counters + 1, (unsigned long long)staged * (unsigned long long)kBlock);
+    }
+    if (ia.acc && ia.ioff[b + 1] - ia.ioff[b] == 1) {
+        // the block's only item: finish here, with the reduction's arithmetic
+        if (lane < nt) {
+            const int64_t i = ia.perm[t];
+            ia.acc[i] = (float)(((double)ax - (double)cx) * X.scale);
+            ia.acc[N + i] = (float)(((double)ay - (double)cy) * X.scale);
+            ia.acc[2 * N + i] = (float)(((double)az - (double)cz) * X.scale);
+        }
+        return;
     }
     float* o = partial + item * 6 * kBlock;
     o[0 * kBlock + lane] = ax;
@@ -398,6 +360,7 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
         const int64_t b = g / kBlock;
         const int l = (int)(g % kBlock);
         if (l >= ia.bcount[b]) continue;
+        if (ia.ioff[b + 1] - ia.ioff[b] == 1) continue;     // written by the PP kernel
         double sx = 0, sy = 0, sz = 0;
         for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) {
             const float* o = partial + it * 6 * kBlock;
@@ -587,10 +550,11 @@ static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int w
 }
 
 int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int waves_per_cu,
-                  int variant, float* partial, unsigned long long* counters, unsigned* queues,
-                  hipStream_t s) {
+                  int variant, float* partial, float* acc, unsigned long long* counters,
+                  unsigned* queues, hipStream_t s) {
+    (void)groups;
     ItemArgs ia = item_args(bd, w, 0);
-    ia.groups = groups;
+    ia.acc = acc;
     switch (variant & 7) {
         case 0: return launch_pp_f32_var<0>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 1: return launch_pp_f32_var<1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);

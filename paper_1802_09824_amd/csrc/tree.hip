@@ -384,7 +384,9 @@ __global__ void block_split_kernel(BatchDev bd, const double* __restrict__ pos_s
 // at once (one thread per entry, children written in order so entries stay
 // sorted by block, shift, node); then one thread per entry walks its
 // subtree (at most 64 leaves) depth-first, testing the 8 children of a node
-// at once.  Leaves (or inside intervals) come in ascending order and
+// at once.  While the entries stay within a memory budget the breadth-first
+// part goes one level further (down to level 1), which leaves a single
+// 8-child test per entry.  Leaves (or inside intervals) come in ascending order and
 // consecutive ones merge into one range of source particles.
 constexpr int kDfsLevel = 2;
 
@@ -462,12 +464,12 @@ template <bool FILL>
 __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                  const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                  const int32_t* __restrict__ bboxid, const FEntry* __restrict__ in,
-                                 int64_t F, int32_t* __restrict__ cnt,
+                                 int64_t F, int stop, int32_t* __restrict__ cnt,
                                  const int64_t* __restrict__ off, FEntry* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= F) return;
     const FEntry E = in[e];
-    if (E.inside || E.lev <= kDfsLevel) {
+    if (E.inside || E.lev <= stop) {
         if (FILL) out[off[e]] = E;
         else cnt[e] = 1;
         return;
@@ -862,19 +864,27 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                        nodes, bbox, bboxid, nb, (int32_t*)nullptr, w.foff.as<int64_t>(),
                        cur->as<FEntry>());
     PP_HIP(hipGetLastError());
-    for (int it = w.max_levels - 1; it > kDfsLevel; --it) {
+    // levels above kDfsLevel must be expanded (the masks cover 64 leaves);
+    // one more level is taken while the expanded entries fit the budget
+    constexpr int64_t kEntryBudget = (int64_t)1 << 26;
+    for (int it = w.max_levels - 1; it >= kDfsLevel; --it) {
+        int stop = kDfsLevel;
+        if (it == kDfsLevel) {                // optional: level 2 -> level 1
+            if (8 * F > kEntryBudget) break;
+            stop = kDfsLevel - 1;
+        }
         PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (F + 1)));
         PP_TRY(w.foff.reserve(sizeof(int64_t) * (F + 2)));
         hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd,
-                           tvs, nodes, bbox, bboxid, cur->as<FEntry>(), F, w.fcnt.as<int32_t>(),
-                           (const int64_t*)nullptr, (FEntry*)nullptr);
+                           tvs, nodes, bbox, bboxid, cur->as<FEntry>(), F, stop,
+                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr);
         PP_HIP(hipGetLastError());
         PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), F, w.scan_ws, s));
         int64_t F2 = 0;
         PP_TRY(read_back(w.foff.as<int64_t>() + F, &F2, s));
         PP_TRY(nxt->reserve(sizeof(FEntry) * (F2 + 1)));
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
-                           nodes, bbox, bboxid, cur->as<FEntry>(), F, (int32_t*)nullptr,
+                           nodes, bbox, bboxid, cur->as<FEntry>(), F, stop, (int32_t*)nullptr,
                            w.foff.as<int64_t>(), nxt->as<FEntry>());
         PP_HIP(hipGetLastError());
         DevBuf* t = cur;
