@@ -256,7 +256,7 @@ struct Batch {
     }
 
     int run_f32(float* acc, hipStream_t s) {
-        PP_TRY(partial.reserve(sizeof(float) * 6 * kBlock * (w.nitem + 1)));
+        PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.nitem + 1)));
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
                 graph_variant != tune.variant * 16 + tune.groups * 256 + tune.waves_per_cu)
@@ -531,7 +531,10 @@ int pp_build_leaves(const uint64_t* sorted_keys, const double* pos_sorted, int64
     pp_leaves* lv = new (std::nothrow) pp_leaves;
     if (!lv) return fail(PP_ENOMEM, "host allocation failed");
     int rc = lv->b.init(1, p, &n, false);
-    if (rc == PP_OK) rc = stage_leaves(lv->b.bd, n, sorted_keys, pos_sorted, lv->b.w, S(stream));
+    if (rc == PP_OK)
+        rc = stage_wrap_copy(lv->b.bd, n, pos_sorted, lv->b.w.pos_s.as<double>(), S(stream));
+    if (rc == PP_OK)
+        rc = stage_leaves(lv->b.bd, n, sorted_keys, lv->b.w.pos_s.as<double>(), lv->b.w, S(stream));
     if (rc == PP_OK) {
         hipError_t e = hipStreamSynchronize(S(stream));
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);

@@ -12,7 +12,6 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
 
 #include "pp_internal.h"
@@ -137,11 +136,45 @@ __global__ void __launch_bounds__(256) gather_kernel(BatchDev bd, const double* 
 
 __global__ void set_zero_i64(int64_t* p) { *p = 0; }
 
+__global__ void __launch_bounds__(256) wrap_copy_kernel(BatchDev bd, const double* __restrict__ in,
+                                                        int64_t N, double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double L = bd.box[box_of(bd.poff, bd.nbox, k)].L;
+    for (int a = 0; a < 3; ++a) {
+        const double x = in[a * N + k];
+        out[a * N + k] = isfinite(x) ? wrap_pos(x, L) : 0.0;
+    }
+}
+
+// Box id (the second sort key) of every particle after the key sort.
+__global__ void __launch_bounds__(256) box_ids_kernel(BatchDev bd, const int32_t* __restrict__ idx,
+                                                      int64_t N, uint16_t* __restrict__ box) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    box[k] = (uint16_t)box_of(bd.poff, bd.nbox, idx[k]);
+}
+
+__global__ void __launch_bounds__(256) gather_keys_kernel(const uint64_t* __restrict__ keys,
+                                                          const int32_t* __restrict__ perm,
+                                                          int64_t N, uint64_t* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    out[k] = keys[perm[k]];
+}
+
 struct to_i64 {
     __device__ __host__ int64_t operator()(int32_t v) const { return (int64_t)v; }
 };
 
 }  // namespace
+
+int stage_wrap_copy(const BatchDev& bd, int64_t N, const double* in, double* out, hipStream_t s) {
+    if (N == 0) return PP_OK;
+    hipLaunchKernelGGL(wrap_copy_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, in, N, out);
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
 
 int stage_keys(const BatchDev& bd, int64_t N, const double* pos, Work& w, hipStream_t s) {
     if (N == 0) return PP_OK;
@@ -161,18 +194,16 @@ int launch_keys_raw(const double* pos, int64_t n, double L, int bits, uint64_t* 
 }
 
 int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes) {
-    size_t b = 0;
-    if (nbox <= 1) {
-        PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b, (const uint64_t*)nullptr,
-                                         (uint64_t*)nullptr, (const int32_t*)nullptr,
-                                         (int32_t*)nullptr, (size_t)n, 0, 3 * bits, (hipStream_t)0));
-    } else {
-        PP_HIP(rocprim::segmented_radix_sort_pairs(
-            (void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, (const int32_t*)nullptr,
-            (int32_t*)nullptr, (unsigned)n, (unsigned)nbox, (const int64_t*)nullptr,
-            (const int64_t*)nullptr, 0, 3 * bits, (hipStream_t)0));
+    size_t b = 0, b2 = 0;
+    PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                     (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0,
+                                     3 * bits, (hipStream_t)0));
+    if (nbox > 1) {
+        PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b2, (const uint16_t*)nullptr,
+                                         (uint16_t*)nullptr, (const int32_t*)nullptr,
+                                         (int32_t*)nullptr, (size_t)n, 0, 16, (hipStream_t)0));
     }
-    *bytes = b;
+    *bytes = b > b2 ? b : b2;
     return PP_OK;
 }
 
@@ -196,12 +227,25 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
         PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, w.keys.as<uint64_t>(),
                                          w.keys_s.as<uint64_t>(), w.iota.as<int32_t>(),
                                          w.perm.as<int32_t>(), (size_t)N, 0, 3 * bd.bits, s));
-    } else {
-        PP_HIP(rocprim::segmented_radix_sort_pairs(
-            w.sort_ws.p, b, w.keys.as<uint64_t>(), w.keys_s.as<uint64_t>(), w.iota.as<int32_t>(),
-            w.perm.as<int32_t>(), (unsigned)N, (unsigned)bd.nbox, bd.poff, bd.poff + 1, 0,
-            3 * bd.bits, s));
+        return PP_OK;
     }
+    // Batches: a stable sort by key, then a stable sort by box id, gives the
+    // (box, key, index) order; both are one-sweep radix sorts over the whole
+    // batch (a per-segment sort is far slower for many small segments).
+    PP_TRY(w.sort_tmp.reserve((sizeof(uint16_t) * 2 + sizeof(int32_t)) * (size_t)(N + 64)));
+    uint16_t* box_a = w.sort_tmp.as<uint16_t>();
+    uint16_t* box_b = box_a + N + 32;
+    int32_t* idx1 = reinterpret_cast<int32_t*>(box_b + N + 32);
+    PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, w.keys.as<uint64_t>(), w.keys_s.as<uint64_t>(),
+                                     w.iota.as<int32_t>(), idx1, (size_t)N, 0, 3 * bd.bits, s));
+    hipLaunchKernelGGL(box_ids_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, idx1, N, box_a);
+    PP_HIP(hipGetLastError());
+    b = w.sort_ws.bytes;
+    PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, box_a, box_b, idx1, w.perm.as<int32_t>(),
+                                     (size_t)N, 0, 16, s));
+    hipLaunchKernelGGL(gather_keys_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s,
+                       w.keys.as<uint64_t>(), w.perm.as<int32_t>(), N, w.keys_s.as<uint64_t>());
+    PP_HIP(hipGetLastError());
     return PP_OK;
 }
 

@@ -132,7 +132,7 @@ struct Work {
     int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
-    DevBuf sort_ws, scan_ws;
+    DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
     DevBuf lam, pmax, smax, level_p, flag, flag_off;
     DevBuf lbegin, lcount, llevel, lprefix, lboxes, loff_dev;
@@ -159,6 +159,8 @@ struct Work {
 // ------------------------------------------------------------- launches --
 // keys_sort.hip
 int stage_keys(const BatchDev& bd, int64_t N, const double* pos, Work& w, hipStream_t s);
+// out = in wrapped into [0, L) per box (the form every later stage expects)
+int stage_wrap_copy(const BatchDev& bd, int64_t N, const double* in, double* out, hipStream_t s);
 int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
 int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* mass_f,
                  const double* mass_d, Work& w, hipStream_t s);
@@ -173,7 +175,7 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
                     int32_t* perm_out, int64_t n, int bits, void* ws, size_t ws_bytes,
                     hipStream_t s);
 
-// tree.hip
+// tree.hip  (positions passed here are wrapped: x - L floor(x / L))
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
                  Work& w, hipStream_t s);
 int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);

@@ -291,13 +291,11 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         }
         return;
     }
-    float* o = partial + item * 6 * kBlock;
-    o[0 * kBlock + lane] = ax;
-    o[1 * kBlock + lane] = ay;
-    o[2 * kBlock + lane] = az;
-    o[3 * kBlock + lane] = cx;
-    o[4 * kBlock + lane] = cy;
-    o[5 * kBlock + lane] = cz;
+    // the compensated sum, rounded once
+    float* o = partial + item * 3 * kBlock;
+    o[0 * kBlock + lane] = (float)((double)ax - (double)cx);
+    o[1 * kBlock + lane] = (float)((double)ay - (double)cy);
+    o[2 * kBlock + lane] = (float)((double)az - (double)cz);
 }
 
 // One workgroup per item.
@@ -363,10 +361,10 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
         if (ia.ioff[b + 1] - ia.ioff[b] == 1) continue;     // written by the PP kernel
         double sx = 0, sy = 0, sz = 0;
         for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) {
-            const float* o = partial + it * 6 * kBlock;
-            sx += (double)o[0 * kBlock + l] - (double)o[3 * kBlock + l];
-            sy += (double)o[1 * kBlock + l] - (double)o[4 * kBlock + l];
-            sz += (double)o[2 * kBlock + l] - (double)o[5 * kBlock + l];
+            const float* o = partial + it * 3 * kBlock;
+            sx += (double)o[0 * kBlock + l];
+            sy += (double)o[1 * kBlock + l];
+            sz += (double)o[2 * kBlock + l];
         }
         const double scale = ia.box[ia.bboxid[b]].scale;
         const int64_t i = perm[(int64_t)ia.bstart[b] + l];

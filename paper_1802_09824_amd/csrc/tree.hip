@@ -25,11 +25,11 @@ namespace pp {
 namespace {
 
 #pragma clang fp contract(off)
-// Grid cell of one coordinate: wrap into [0, L) as x - L floor(x / L) (an
-// identity for already wrapped values), then floor(w 2^b / L) clamped, each
-// operation rounded on its own exactly as in the key kernel.
-__device__ __forceinline__ uint32_t quantise_w(double x, double L, double scale, uint32_t qmax) {
-    double w = x - L * floor(x / L);
+// Grid cell of one coordinate of an already wrapped position w (the gather
+// stores x - L floor(x / L)): floor(w 2^b / L) clamped, exactly the
+// quantisation the key kernel applies to the same wrapped value.
+__device__ __forceinline__ uint32_t quantise_w(double w, double L, double scale, uint32_t qmax) {
+    (void)L;
     double f = floor(w * scale);
     if (!(f > 0.0)) return 0u;
     if (f > (double)qmax) return qmax;
@@ -312,23 +312,74 @@ __global__ void canon_kernel(TreeView tv, const IBox* __restrict__ nodes, int64_
 }
 
 // -------------------------------------------------------- target blocks --
-// One thread per chunk of kBlock consecutive particles of one box walks the
-// chunk and starts a new block whenever adding the next particle would make
-// the bounding box wider than emax grid units along some axis.
+// One wave per chunk of kBlock consecutive particles of one box.  Every
+// lane quantises its particle; if the chunk's bounding box is at most emax
+// grid units wide along every axis (the common case) the chunk is one
+// block.  Otherwise lane 0 walks the chunk and starts a new block whenever
+// adding the next particle would make the box wider than emax.
+__device__ __forceinline__ int32_t wave_min_i(int32_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const int32_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int32_t wave_max_i(int32_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const int32_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
 template <bool FILL>
-__global__ void block_split_kernel(BatchDev bd, const double* __restrict__ pos_s, int64_t N,
-                                   const int64_t* __restrict__ choff, int64_t nchunk,
-                                   int32_t* __restrict__ ccount, const int64_t* __restrict__ coff,
-                                   int32_t* __restrict__ bstart, int32_t* __restrict__ bcount,
-                                   IBox* __restrict__ box, int32_t* __restrict__ bboxid) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(64) block_split_kernel(
+    BatchDev bd, const double* __restrict__ pos_s, int64_t N, const int64_t* __restrict__ choff,
+    int64_t nchunk, int32_t* __restrict__ ccount, const int64_t* __restrict__ coff,
+    int32_t* __restrict__ bstart, int32_t* __restrict__ bcount, IBox* __restrict__ box,
+    int32_t* __restrict__ bboxid) {
+    const int64_t c = blockIdx.x;
     if (c >= nchunk) return;
+    const int lane = threadIdx.x;
     const int x = box_of(choff, bd.nbox, c);
     const BoxDev& X = bd.box[x];
     const uint32_t qmax = (uint32_t)(X.W - 1);
     const int64_t k0 = X.poff + (c - choff[x]) * kBlock;
     const int64_t kend = X.poff + X.n;
     const int64_t k1 = k0 + kBlock < kend ? k0 + kBlock : kend;
+    const int64_t k = k0 + lane;
+    const bool valid = k < k1;
+    __shared__ int32_t qs[3][kBlock];
+    int32_t lo[3], hi[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t q = valid ? (int32_t)quantise_w(pos_s[ax * N + k], X.L, X.qscale, qmax) : 0;
+        qs[ax][lane] = q;
+        lo[ax] = wave_min_i(valid ? q : INT32_MAX);
+        hi[ax] = wave_max_i(valid ? q + 1 : INT32_MIN);
+    }
+    const bool fits = (int64_t)(hi[0] - lo[0]) <= X.emax && (int64_t)(hi[1] - lo[1]) <= X.emax &&
+                      (int64_t)(hi[2] - lo[2]) <= X.emax;
+    if (fits) {
+        if (lane == 0) {
+            if (FILL) {
+                const int64_t o = coff[c];
+                bstart[o] = (int32_t)k0;
+                bcount[o] = (int32_t)(k1 - k0);
+                IBox B;
+                for (int ax = 0; ax < 3; ++ax) {
+                    B.lo[ax] = lo[ax];
+                    B.hi[ax] = hi[ax];
+                }
+                box[o] = B;
+                bboxid[o] = x;
+            } else {
+                ccount[c] = 1;
+            }
+        }
+        return;
+    }
+    __syncthreads();
+    if (lane != 0) return;
     int64_t o = FILL ? coff[c] : 0;
     int32_t nb = 0;
     int64_t start = k0;
@@ -342,11 +393,10 @@ __global__ void block_split_kernel(BatchDev bd, const double* __restrict__ pos_s
         }
         ++nb;
     };
-    for (int64_t k = k0; k < k1; ++k) {
-        int32_t q[3];
-        for (int ax = 0; ax < 3; ++ax)
-            q[ax] = (int32_t)quantise_w(pos_s[ax * N + k], X.L, X.qscale, qmax);
-        if (k == start) {
+    for (int64_t kk = k0; kk < k1; ++kk) {
+        const int l = (int)(kk - k0);
+        const int32_t q[3] = {qs[0][l], qs[1][l], qs[2][l]};
+        if (kk == start) {
             for (int ax = 0; ax < 3; ++ax) {
                 B.lo[ax] = q[ax];
                 B.hi[ax] = q[ax] + 1;
@@ -361,8 +411,8 @@ __global__ void block_split_kernel(BatchDev bd, const double* __restrict__ pos_s
             wide |= (int64_t)(U.hi[ax] - U.lo[ax]) > X.emax;
         }
         if (wide) {
-            emit(k);
-            start = k;
+            emit(kk);
+            start = kk;
             for (int ax = 0; ax < 3; ++ax) {
                 B.lo[ax] = q[ax];
                 B.hi[ax] = q[ax] + 1;
@@ -820,7 +870,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.ccount.reserve(sizeof(int32_t) * nc));
     PP_TRY(w.coff.reserve(sizeof(int64_t) * (nc + 1)));
     const double* pos_s = w.pos_s.as<double>();
-    hipLaunchKernelGGL(block_split_kernel<false>, dim3(blocks_for(nc, 128)), dim3(128), 0, s, bd,
+    hipLaunchKernelGGL(block_split_kernel<false>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
                        pos_s, N, w.choff.as<int64_t>(), nc, w.ccount.as<int32_t>(),
                        (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
                        (IBox*)nullptr, (int32_t*)nullptr);
@@ -838,7 +888,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.icount.reserve(sizeof(int32_t) * nb));
     PP_TRY(w.ioff.reserve(sizeof(int64_t) * (nb + 1)));
     PP_TRY(w.misc.reserve(64));
-    hipLaunchKernelGGL(block_split_kernel<true>, dim3(blocks_for(nc, 128)), dim3(128), 0, s, bd,
+    hipLaunchKernelGGL(block_split_kernel<true>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
                        pos_s, N, w.choff.as<int64_t>(), nc, (int32_t*)nullptr,
                        w.coff.as<int64_t>(), w.bstart.as<int32_t>(), w.bcount.as<int32_t>(),
                        w.bbox.as<IBox>(), w.bboxid.as<int32_t>());
@@ -864,15 +914,11 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                        nodes, bbox, bboxid, nb, (int32_t*)nullptr, w.foff.as<int64_t>(),
                        cur->as<FEntry>());
     PP_HIP(hipGetLastError());
-    // levels above kDfsLevel must be expanded (the masks cover 64 leaves);
-    // one more level is taken while the expanded entries fit the budget
-    constexpr int64_t kEntryBudget = (int64_t)1 << 26;
+    // Levels above kDfsLevel must be expanded (the masks cover 64 leaves);
+    // level 2 -> 1 is taken too when the expanded entries fit the budget.
+    constexpr int64_t kEntryBudget = (int64_t)1 << 27;
     for (int it = w.max_levels - 1; it >= kDfsLevel; --it) {
-        int stop = kDfsLevel;
-        if (it == kDfsLevel) {                // optional: level 2 -> level 1
-            if (8 * F > kEntryBudget) break;
-            stop = kDfsLevel - 1;
-        }
+        const int stop = it == kDfsLevel ? kDfsLevel - 1 : kDfsLevel;
         PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (F + 1)));
         PP_TRY(w.foff.reserve(sizeof(int64_t) * (F + 2)));
         hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd,
@@ -882,6 +928,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), F, w.scan_ws, s));
         int64_t F2 = 0;
         PP_TRY(read_back(w.foff.as<int64_t>() + F, &F2, s));
+        if (it == kDfsLevel && F2 > kEntryBudget) break;      // stay at level 2
         PP_TRY(nxt->reserve(sizeof(FEntry) * (F2 + 1)));
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                            nodes, bbox, bboxid, cur->as<FEntry>(), F, stop, (int32_t*)nullptr,

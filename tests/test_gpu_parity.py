@@ -89,10 +89,14 @@ def leaves_case(name):
         return rng.random((3, 7)) * 10.0, BoxParams(L=10.0, rs=1.0, rcut=4.5, eps=0.0, leaf_max=32)
     if name == "coarse-bits":
         return small_clustered(5000, 30.0, 0.5, 5, 2), BoxParams(L=30.0, rs=1.0, rcut=4.5, eps=0.01, leaf_max=4, key_bits=6)
+    if name == "edge-wrap":
+        # coordinates that wrap to exactly L (clamped into the last cell), to 0,
+        # and from several periods away: keys, leaf boxes and blocks must agree
+        return edge_positions(37.5, np.random.default_rng(12)), BoxParams(L=37.5, rs=1.0, rcut=4.5, eps=0.01, leaf_max=8)
     raise KeyError(name)
 
 
-LEAF_CASES = ["cfg1", "clustered-lm8", "duplicates", "tiny", "coarse-bits"]
+LEAF_CASES = ["cfg1", "clustered-lm8", "duplicates", "tiny", "coarse-bits", "edge-wrap"]
 
 
 @pytest.mark.parametrize("case", LEAF_CASES)
@@ -110,7 +114,7 @@ def test_leaves_bit_exact(pp, oracle_mod, case):
     assert np.array_equal(got["hi"].astype(np.int64), st["hi"])
 
 
-@pytest.mark.parametrize("case", ["clustered-lm8", "duplicates", "tiny", "coarse-bits", "cfg1"])
+@pytest.mark.parametrize("case", ["clustered-lm8", "duplicates", "tiny", "coarse-bits", "cfg1", "edge-wrap"])
 def test_near_pairs_bit_exact(pp, oracle_mod, case):
     pos, p = leaves_case(case)
     st = oracle_mod.structure(pos, p)
@@ -180,6 +184,7 @@ EDGE_CASES = {
     "coincident-eps0": lambda: (np.concatenate([np.full((3, 5), 2.5), np.random.default_rng(1).random((3, 200)) * 10], axis=1), BoxParams(L=10.0, rs=0.5, rcut=2.25, eps=0.0)),
     "wide-cut": lambda: (np.random.default_rng(2).random((3, 2000)) * 10, BoxParams(L=10.0, rs=1.1, rcut=4.95, eps=0.01)),
     "unwrapped": lambda: (np.random.default_rng(3).random((3, 1500)) * 60 - 20, BoxParams(L=20.0, rs=1.0, rcut=4.5, eps=0.01)),
+    "edge-wrap": lambda: (edge_positions(37.5, np.random.default_rng(12)), BoxParams(L=37.5, rs=1.0, rcut=4.5, eps=0.01)),
     "lattice": lambda: (W.lattice(8, 8.0), BoxParams(L=8.0, rs=0.6, rcut=2.7, eps=0.02)),
     "leaf1": lambda: (np.random.default_rng(4).random((3, 1000)) * 20, BoxParams(L=20.0, rs=1.0, rcut=4.5, eps=0.01, leaf_max=1)),
     "leaf1024": lambda: (small_clustered(5000, 30.0, 0.6, 4, 8), BoxParams(L=30.0, rs=1.0, rcut=4.5, eps=0.01, leaf_max=1024)),
