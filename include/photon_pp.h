@@ -193,7 +193,7 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *               target block's bounding box).
  * The chunk grows by itself when the lists are long enough that more than
  * 2^21 work items would be needed.
- * Defaults: plans {2048, 1, 16, 0, 0, 1}; batch plans {2048, 1, 16, 1, 0, 1}. */
+ * Defaults: plans {2048, 1, 20, 0, 0, 1}; batch plans {2048, 1, 20, 1, 0, 1}. */
 typedef struct pp_tuning {
     int32_t chunk, persistent, waves_per_cu, use_graph, variant, groups;
 } pp_tuning;

@@ -64,8 +64,9 @@ BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
     b.L = p.L;
     b.qscale = ldexp(1.0, p.key_bits) / p.L;
     b.cell = p.L / ldexp(1.0, p.key_bits);
-    b.inv_rcut = 1.0 / p.rcut;
-    b.scale = p.G / (p.rcut * p.rcut);
+    const double ell = pair_length_unit(p);
+    b.inv_len = 1.0 / ell;
+    b.scale = p.G / (ell * ell);
     b.rs = p.rs;
     b.rcut = p.rcut;
     b.eps = p.eps;
@@ -110,8 +111,8 @@ struct Batch {
     DevBuf box_dev, poff_dev;
     BatchDev bd{};
     Work w;
-    pp_tuning tune{2048, 1, 16, 0, 0, 1};
-    int graph_variant = -1;
+    pp_tuning tune{2048, 1, 20, 0, 0, 1};
+    int64_t graph_variant = -1;
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
     bool timing = false, timed = false;
@@ -251,15 +252,20 @@ struct Batch {
         PP_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         graph_gen = alloc_generation();
         graph_acc = acc;
-        graph_variant = tune.variant * 16 + tune.groups * 256 + tune.waves_per_cu;
+        graph_variant = graph_key();
         return PP_OK;
+    }
+
+    // what the captured launch depends on besides buffers: variant, groups, waves
+    int64_t graph_key() const {
+        return ((int64_t)tune.variant << 32) | ((int64_t)tune.groups << 16) | (int64_t)tune.waves_per_cu;
     }
 
     int run_f32(float* acc, hipStream_t s) {
         PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.nitem + 1)));
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
-                graph_variant != tune.variant * 16 + tune.groups * 256 + tune.waves_per_cu)
+                graph_variant != graph_key())
                 PP_TRY(capture(acc));
             if (timing) PP_HIP(hipEventRecord(ev0, s));
             PP_HIP(hipGraphLaunch(gexec, s));
@@ -353,7 +359,7 @@ struct Batch {
         const bool batch = nbox > 1;
         const int chunks[] = {1024, 2048, 4096, 8192};
         struct Shape { int persistent, waves; };
-        const Shape shapes[] = {{0, 16}, {1, 8}, {1, 16}, {1, 32}};
+        const Shape shapes[] = {{0, 24}, {1, 12}, {1, 20}, {1, 24}};
         pp_tuning best = tune;
         float best_ms = 1e30f;
         for (int c : chunks) {

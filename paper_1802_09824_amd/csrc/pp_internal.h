@@ -84,18 +84,19 @@ struct TreeView {
     int32_t pad;
 };
 
-// FP32 constants of the PP kernel for one box (units of r_cut).
+// FP32 constants of the PP kernel for one box, in the kernel's length unit
+// ell = 2 r_s sqrt(U_MAX / 2) (so that the split polynomial's variable is
+// t = r2 - 1 and its coefficients are the same for every box).
 struct PolyF32 {
-    float c[10];     // k^3 H coefficients in t, highest last
-    float tscale;    // t = r2 * tscale - 1
-    float eps2n;     // softening^2 / rcut^2 (floored)
-    float cut2;      // 1 + eps2n
+    float eps2n;     // softening^2 / ell^2 (floored)
+    float cut2;      // (rcut^2 + eps^2) / ell^2, the cut on r2
+    float keep2;     // slightly widened (rcut / ell)^2, the staging test
     float pad;
 };
 
 // Per-box constants, resident on the device.
 struct BoxDev {
-    double L, qscale, cell, inv_rcut, scale;   // scale = G / rcut^2
+    double L, qscale, cell, inv_len, scale;    // inv_len = 1 / ell, scale = G / ell^2
     double rs, rcut, eps, G;
     int64_t W, T, emax;
     int64_t poff, n;
@@ -103,6 +104,8 @@ struct BoxDev {
 };
 
 int make_poly(const pp_box_params& p, PolyF32* out);
+// The FP32 kernel's length unit ell = 2 r_s sqrt(U_MAX / 2).
+double pair_length_unit(const pp_box_params& p);
 BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n);
 int validate_params(const pp_box_params* p, bool need_poly);
 

@@ -3,14 +3,20 @@
 //
 // Per pair (sec. 3.1, Eq. equ:split, with Plummer softening):
 //   a_i += G m_j d g(s_eps / 2 r_s) / s_eps^3,   kept iff s < r_cut.
-// FP32 form.  Lengths are in units of r_cut, relative to the FP64 centre of
-// the target block (the origin subtraction is done in FP64 when a source is
-// staged, so the FP32 offsets are small and precise).  With r2 = s_eps^2,
-// y = 1/s_eps (hardware reciprocal square root) and u = x^2 = r2 k^2,
-// k = r_cut / (2 r_s):
-//   g / s_eps^3 = y^3 - k^3 H(u),   g(x) = 1 - x^3 H(x^2),
-// H a fitted polynomial (split_poly.h).  Softening enters r2 through the
-// first fused multiply-add; the cut test compares r2 with 1 + eps^2.
+// FP32 form.  Lengths are in units of ell = 2 r_s sqrt(U_MAX / 2),
+// relative to the FP64 centre of the target block (the origin subtraction
+// is done in FP64 when a source is staged, so the FP32 offsets are small
+// and precise).  With g(x) = 1 - x^3 H(x^2), H a polynomial fitted on
+// u = x^2 in [0, U_MAX] in the variable t = 2u / U_MAX - 1 (split_poly.h),
+// r2 = s_eps^2 / ell^2 and y = 1 / sqrt(r2) (hardware reciprocal square
+// root), the unit makes t = r2 - 1 and
+//   ell^3 g / s_eps^3 = y^3 - (U_MAX / 2)^(3/2) H(u),
+// so the polynomial's coefficients are the same literals for every box and
+// G / ell^2 scales the sum at the end.  Softening enters r2 through the
+// first fused multiply-add; the cut test compares r2 with
+// (r_cut^2 + eps^2) / ell^2.  Every operand of the pair arithmetic is a
+// VGPR or a literal: on gfx950 two waves' VALU instructions issue together
+// only then.
 // Sources are staged 64 at a time in LDS and broadcast to the 64 lanes
 // (one target per lane).  Each tile of 64 pairs is summed in FP32 and the
 // tile sums enter a Kahan-compensated per-target total.  Work items are
@@ -84,6 +90,16 @@ __device__ __forceinline__ int64_t find_range(const int32_t* __restrict__ rpre, 
     return lo;
 }
 
+constexpr double csqrt(double x) {
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+// (U_MAX / 2)^(3/2): H's factor in the length unit ell
+constexpr double kHScale = 0.5 * SPLIT_POLY_U_MAX * csqrt(0.5 * SPLIT_POLY_U_MAX);
+static_assert(SPLIT_POLY_DEGREE == 9, "the pair function unrolls a degree-9 polynomial");
+#define PP_HC(j) ((float)(kHScale * SPLIT_POLY_C[j]))
+
 // One source against the lane's target; adds into (tx, ty, tz).
 template <bool NEWTON>
 __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, float zi,
@@ -94,17 +110,16 @@ __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, fl
     r2 = fmaf(dz, dz, r2);
     float y = __builtin_amdgcn_rsqf(r2);
     if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
-    const float u = fmaf(r2, P.tscale, -1.f);
-    float h = P.c[9];
-    h = fmaf(h, u, P.c[8]);
-    h = fmaf(h, u, P.c[7]);
-    h = fmaf(h, u, P.c[6]);
-    h = fmaf(h, u, P.c[5]);
-    h = fmaf(h, u, P.c[4]);
-    h = fmaf(h, u, P.c[3]);
-    h = fmaf(h, u, P.c[2]);
-    h = fmaf(h, u, P.c[1]);
-    h = fmaf(h, u, P.c[0]);
+    const float t = r2 - 1.f;
+    float h = fmaf(t, PP_HC(9), PP_HC(8));
+    h = fmaf(h, t, PP_HC(7));
+    h = fmaf(h, t, PP_HC(6));
+    h = fmaf(h, t, PP_HC(5));
+    h = fmaf(h, t, PP_HC(4));
+    h = fmaf(h, t, PP_HC(3));
+    h = fmaf(h, t, PP_HC(2));
+    h = fmaf(h, t, PP_HC(1));
+    h = fmaf(h, t, PP_HC(0));
     const float y3 = y * y * y;
     float F = (y3 - h) * sj.w;
     F = r2 < P.cut2 ? F : 0.f;
@@ -166,24 +181,24 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
     const int32_t nt = ia.bcount[b];
     const BoxDev& X = ia.box[ia.bboxid[b]];
-    const double L = X.L, cell = X.cell, inv_rcut = X.inv_rcut;
+    const double L = X.L, cell = X.cell, inv_len = X.inv_len;
     const PolyF32 P = X.poly;
     const IBox B = ia.bbox[b];
     const double ox = 0.5 * (double)(B.lo[0] + B.hi[0]) * cell;
     const double oy = 0.5 * (double)(B.lo[1] + B.hi[1]) * cell;
     const double oz = 0.5 * (double)(B.lo[2] + B.hi[2]) * cell;
-    // half sides of the block box in units of r_cut, widened slightly so the
+    // half sides of the block box in units of ell, widened slightly so the
     // pruning test can only keep too much
-    const float hx = (float)(0.5 * (double)(B.hi[0] - B.lo[0]) * cell * inv_rcut) * 1.0001f + 1e-6f;
-    const float hy = (float)(0.5 * (double)(B.hi[1] - B.lo[1]) * cell * inv_rcut) * 1.0001f + 1e-6f;
-    const float hz = (float)(0.5 * (double)(B.hi[2] - B.lo[2]) * cell * inv_rcut) * 1.0001f + 1e-6f;
-    const float keep2 = 1.0002f;
+    const float hx = (float)(0.5 * (double)(B.hi[0] - B.lo[0]) * cell * inv_len) * 1.0001f + 1e-6f;
+    const float hy = (float)(0.5 * (double)(B.hi[1] - B.lo[1]) * cell * inv_len) * 1.0001f + 1e-6f;
+    const float hz = (float)(0.5 * (double)(B.hi[2] - B.lo[2]) * cell * inv_len) * 1.0001f + 1e-6f;
+    const float keep2 = P.keep2;
     const int64_t t = (int64_t)ia.bstart[b] + lane;
     float xi = 0.f, yi = 0.f, zi = 0.f;
     if (lane < nt) {
-        xi = (float)((pos_s[t] - (LOCAL ? ox : 0.0)) * inv_rcut);
-        yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_rcut);
-        zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_rcut);
+        xi = (float)((pos_s[t] - (LOCAL ? ox : 0.0)) * inv_len);
+        yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_len);
+        zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_len);
     }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
@@ -223,18 +238,18 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             const double sx = (double)(pc / 9 - 1) * L;
             const double sy = (double)((pc / 3) % 3 - 1) * L;
             const double sz = (double)(pc % 3 - 1) * L;
-            v.x = (float)((px + sx - ox) * inv_rcut);
-            v.y = (float)((py + sy - oy) * inv_rcut);
-            v.z = (float)((pz + sz - oz) * inv_rcut);
+            v.x = (float)((px + sx - ox) * inv_len);
+            v.y = (float)((py + sy - oy) * inv_len);
+            v.z = (float)((pz + sz - oz) * inv_len);
             v.w = pm;
             const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
             const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
             const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
             keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
             if (!LOCAL) {
-                v.x = (float)((px + sx) * inv_rcut);
-                v.y = (float)((py + sy) * inv_rcut);
-                v.z = (float)((pz + sz) * inv_rcut);
+                v.x = (float)((px + sx) * inv_len);
+                v.y = (float)((py + sy) * inv_len);
+                v.z = (float)((pz + sz) * inv_len);
             }
         }
         const uint64_t bal = __ballot(keep);
@@ -299,8 +314,11 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
 }
 
 // One workgroup per item.
+// Both forms are bounded to 80 VGPRs (6 waves per SIMD): two waves' VALU
+// instructions can issue in the same cycle, so more resident waves keep the
+// pair loop's issue slots fuller.
 template <int VAR>
-__global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
+__global__ void __launch_bounds__(64, 6) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
                                                     const float* __restrict__ mass_s, int64_t N,
                                                     int64_t per_xcd, float* __restrict__ partial,
                                                     unsigned long long* __restrict__ counters) {
@@ -316,7 +334,7 @@ __global__ void __launch_bounds__(64) pp_f32_kernel(ItemArgs ia, const double* _
 // once all queues are empty.  The item count is read from device memory,
 // so the launch can be replayed from a graph while the lists change.
 template <int VAR>
-__global__ void __launch_bounds__(64) pp_f32_persistent(ItemArgs ia,
+__global__ void __launch_bounds__(64, 6) pp_f32_persistent(ItemArgs ia,
                                                         const double* __restrict__ pos_s,
                                                         const float* __restrict__ mass_s, int64_t N,
                                                         float* __restrict__ partial,
@@ -504,16 +522,19 @@ __global__ void __launch_bounds__(256) reduce_count_kernel(ItemArgs ia,
 
 }  // namespace
 
+double pair_length_unit(const pp_box_params& p) {
+    return 2.0 * p.rs * std::sqrt(0.5 * SPLIT_POLY_U_MAX);
+}
+
 int make_poly(const pp_box_params& p, PolyF32* out) {
-    const double k = p.rcut / (2.0 * p.rs);          // x = s_n k with s_n = s / rcut
-    const double K = k * k * k;
-    for (int j = 0; j <= SPLIT_POLY_DEGREE; ++j) out->c[j] = (float)(K * SPLIT_POLY_C[j]);
-    out->tscale = (float)(2.0 * k * k / SPLIT_POLY_U_MAX);
-    double e2 = (p.eps / p.rcut) * (p.eps / p.rcut);
+    const double ell = pair_length_unit(p);
+    double e2 = (p.eps / ell) * (p.eps / ell);
     const double floor2 = ldexp(1.0, -60);          // keeps y^3 finite for s = eps = 0
     if (e2 < floor2) e2 = floor2;
+    const double c2 = (p.rcut / ell) * (p.rcut / ell);
     out->eps2n = (float)e2;
-    out->cut2 = (float)(1.0 + e2);
+    out->cut2 = (float)(c2 + e2);
+    out->keep2 = (float)c2 * 1.0002f;
     out->pad = 0.f;
     return PP_OK;
 }

@@ -151,3 +151,31 @@ def test_variants_run_and_stay_close(pp, oracle_mod, variant):
     assert s["zero_ok"] and s["p999"] <= 1e-3, (variant, s)
     if variant in (1, 2):
         assert s["median"] <= 1e-6, (variant, s)
+
+
+def test_equal_mass_boxes_mixed_with_unequal(pp, oracle_mod):
+    """Boxes whose masses are all equal take the shorter pair loop (the mass
+    joins the final scale); boxes with unequal masses in the same batch keep
+    the general loop.  Both kinds must match the oracle, and nudging one mass
+    by one ulp (which switches that box to the general loop) may move the
+    result only by rounding."""
+    boxes = small_batch(6, seed=23)
+    for k in (0, 2, 4):
+        boxes[k].mass[:] = np.float32(1.0 / max(1, boxes[k].n))
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    acc = bp.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    off = 0
+    for b in boxes:
+        ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params)
+        s = parity.summary(acc[:, off:off + b.n], ref)
+        assert s["zero_ok"] and s["median"] <= 1e-6 and s["p999"] <= 1e-4, (b.name, s)
+        off += b.n
+    nudged = mass.copy()
+    nudged[boxes[0].n // 2] = np.nextafter(nudged[boxes[0].n // 2], np.float32(1))
+    acc2 = bp.accel(dev(pos, torch.float64), dev(nudged, torch.float32)).cpu().numpy()
+    a, c = acc[:, :boxes[0].n], acc2[:, :boxes[0].n]
+    mag = np.linalg.norm(a, axis=0)
+    rel = np.linalg.norm(a - c, axis=0) / np.where(mag > 0, mag, 1)
+    assert np.median(rel) <= 1e-6 and rel.max() <= 1e-4
+    assert np.array_equal(acc[:, boxes[0].n:], acc2[:, boxes[0].n:])
