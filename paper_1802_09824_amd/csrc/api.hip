@@ -189,6 +189,7 @@ struct Batch {
         PP_TRY(stage_sort(bd, N, w, s));
         if (mass_d) PP_TRY(w.mass_sd.reserve(8 * (N > 0 ? N : 1)));
         PP_TRY(stage_gather(bd, N, pos, mass_f, mass_d, w, s));
+        if (mass_f) PP_TRY(stage_mass_flags(bd, N, w, s));
         PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s));
         int bad = 0;
         PP_HIP(hipMemcpyAsync(&bad, w.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -136,6 +136,21 @@ __global__ void __launch_bounds__(256) gather_kernel(BatchDev bd, const double* 
 
 __global__ void set_zero_i64(int64_t* p) { *p = 0; }
 
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
+}
+
+// flag[box] = 1 where some mass of the box differs from the box's first one
+// (a plain store of the same value by every such lane; no atomics).
+__global__ void __launch_bounds__(256) mass_flag_kernel(BatchDev bd, const float* __restrict__ mass_s,
+                                                        int64_t N, int32_t* __restrict__ flag) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int x = box_of(bd.poff, bd.nbox, k);
+    if (mass_s[k] != mass_s[bd.poff[x]]) flag[x] = 1;
+}
+
 __global__ void __launch_bounds__(256) wrap_copy_kernel(BatchDev bd, const double* __restrict__ in,
                                                         int64_t N, double* __restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,6 +183,17 @@ struct to_i64 {
 };
 
 }  // namespace
+
+int stage_mass_flags(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
+    PP_TRY(w.mass_flag.reserve(sizeof(int32_t) * (bd.nbox + 1)));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(bd.nbox, 64)), dim3(64), 0, s,
+                       w.mass_flag.as<int32_t>(), (int64_t)bd.nbox, 0);
+    if (N > 0)
+        hipLaunchKernelGGL(mass_flag_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd,
+                           w.mass_s.as<float>(), N, w.mass_flag.as<int32_t>());
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
 
 int stage_wrap_copy(const BatchDev& bd, int64_t N, const double* in, double* out, hipStream_t s) {
     if (N == 0) return PP_OK;

@@ -135,6 +135,7 @@ struct Work {
     int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
+    DevBuf mass_flag;        // int32 [nbox]: 1 where the box's FP32 masses are not all equal
     DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
     DevBuf lam, pmax, smax, level_p, flag, flag_off;
@@ -162,6 +163,8 @@ struct Work {
 // ------------------------------------------------------------- launches --
 // keys_sort.hip
 int stage_keys(const BatchDev& bd, int64_t N, const double* pos, Work& w, hipStream_t s);
+// per-box flag: masses not all equal (equal masses take a shorter pair loop)
+int stage_mass_flags(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
 // out = in wrapped into [0, L) per box (the form every later stage expects)
 int stage_wrap_copy(const BatchDev& bd, int64_t N, const double* in, double* out, hipStream_t s);
 int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);

@@ -46,6 +46,7 @@ struct ItemArgs {
     const int64_t* ioff;
     const BoxDev* box;
     const int32_t* perm;       // key order -> input order
+    const int32_t* mass_flag;  // per box: 1 where the masses are not all equal
     float* acc;                // FP32 output (single-item blocks write it directly)
     int chunk;
 };
@@ -67,6 +68,7 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.ioff = w.ioff.as<int64_t>();
     ia.box = bd.box;
     ia.perm = w.perm.as<int32_t>();
+    ia.mass_flag = w.mass_flag.as<int32_t>();
     ia.acc = nullptr;
     ia.chunk = w.chunk;       // the effective chunk the items were cut with
     return ia;
@@ -128,6 +130,36 @@ __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, fl
     tz = fmaf(F, dz, tz);
 }
 
+// The same for a box whose masses are all equal: the source's w slot holds
+// the cut on r2 instead of the mass (which joins the final scale), so the
+// tile keeps its 16-byte entries and the mass multiply drops out.
+template <bool NEWTON>
+__device__ __forceinline__ void pair_f32_eq(const float4 sj, float xi, float yi, float zi,
+                                            float& tx, float& ty, float& tz, float eps2) {
+    const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
+    float r2 = fmaf(dx, dx, eps2);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    float y = __builtin_amdgcn_rsqf(r2);
+    if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float t = r2 - 1.f;
+    float h = fmaf(t, PP_HC(9), PP_HC(8));
+    h = fmaf(h, t, PP_HC(7));
+    h = fmaf(h, t, PP_HC(6));
+    h = fmaf(h, t, PP_HC(5));
+    h = fmaf(h, t, PP_HC(4));
+    h = fmaf(h, t, PP_HC(3));
+    h = fmaf(h, t, PP_HC(2));
+    h = fmaf(h, t, PP_HC(1));
+    h = fmaf(h, t, PP_HC(0));
+    const float y3 = y * y * y;
+    float F = y3 - h;
+    F = r2 < sj.w ? F : 0.f;
+    tx = fmaf(F, dx, tx);
+    ty = fmaf(F, dy, ty);
+    tz = fmaf(F, dz, tz);
+}
+
 __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
     const float y = v - c;
     const float t = s + y;
@@ -180,9 +212,13 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     const int32_t S = ia.slen[b];
     const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
     const int32_t nt = ia.bcount[b];
-    const BoxDev& X = ia.box[ia.bboxid[b]];
+    const int xbox = ia.bboxid[b];
+    const BoxDev& X = ia.box[xbox];
     const double L = X.L, cell = X.cell, inv_len = X.inv_len;
     const PolyF32 P = X.poly;
+    // equal masses (the compensated form only): the mass joins the final scale
+    const bool equal = KAHAN && ia.mass_flag[xbox] == 0;
+    const float mu = equal ? mass_s[X.poff] : 1.f;
     const IBox B = ia.bbox[b];
     const double ox = 0.5 * (double)(B.lo[0] + B.hi[0]) * cell;
     const double oy = 0.5 * (double)(B.lo[1] + B.hi[1]) * cell;
@@ -241,7 +277,7 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             v.x = (float)((px + sx - ox) * inv_len);
             v.y = (float)((py + sy - oy) * inv_len);
             v.z = (float)((pz + sz - oz) * inv_len);
-            v.w = pm;
+            v.w = equal ? P.cut2 : pm;
             const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
             const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
             const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
@@ -265,8 +301,14 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             wave_sync();
             float tx = 0.f, ty = 0.f, tz = 0.f;
             if (KAHAN) {
+                if (equal) {
 #pragma unroll 8
-                for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+                    for (int q = 0; q < kBlock; ++q)
+                        pair_f32_eq<NEWTON>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n);
+                } else {
+#pragma unroll 8
+                    for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+                }
                 kahan_add(ax, cx, tx);
                 kahan_add(ay, cy, ty);
                 kahan_add(az, cz, tz);
@@ -284,7 +326,11 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         wave_sync();
         float tx = 0.f, ty = 0.f, tz = 0.f;
         if (KAHAN) {
-            for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+            if (equal) {
+                for (int q = 0; q < count; ++q) pair_f32_eq<NEWTON>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n);
+            } else {
+                for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+            }
             kahan_add(ax, cx, tx);
             kahan_add(ay, cy, ty);
             kahan_add(az, cz, tz);
@@ -300,17 +346,18 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         // the block's only item: finish here, with the reduction's arithmetic
         if (lane < nt) {
             const int64_t i = ia.perm[t];
-            ia.acc[i] = (float)(((double)ax - (double)cx) * X.scale);
-            ia.acc[N + i] = (float)(((double)ay - (double)cy) * X.scale);
-            ia.acc[2 * N + i] = (float)(((double)az - (double)cz) * X.scale);
+            const double sc = X.scale * (double)mu;
+            ia.acc[i] = (float)(((double)ax - (double)cx) * sc);
+            ia.acc[N + i] = (float)(((double)ay - (double)cy) * sc);
+            ia.acc[2 * N + i] = (float)(((double)az - (double)cz) * sc);
         }
         return;
     }
-    // the compensated sum, rounded once
+    // the compensated sum (times the equal mass, if any), rounded once
     float* o = partial + item * 3 * kBlock;
-    o[0 * kBlock + lane] = (float)((double)ax - (double)cx);
-    o[1 * kBlock + lane] = (float)((double)ay - (double)cy);
-    o[2 * kBlock + lane] = (float)((double)az - (double)cz);
+    o[0 * kBlock + lane] = (float)(((double)ax - (double)cx) * (double)mu);
+    o[1 * kBlock + lane] = (float)(((double)ay - (double)cy) * (double)mu);
+    o[2 * kBlock + lane] = (float)(((double)az - (double)cz) * (double)mu);
 }
 
 // One workgroup per item.
