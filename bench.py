@@ -26,11 +26,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PP pair-interactions/s and % FP32 VALU peak; batched vs plain at fixed error"
 # FP32 operations the PP kernel performs per evaluated pair (an FMA counts 2):
-# 3 sub (d), 3 FMA (s^2 + eps^2), 1 rsqrt, 1 FMA (polynomial variable),
-# 9 FMA (polynomial), 1 mul + 1 FMA (y^3 - k^3 H), 1 mul (mass), 3 FMA (sum).
-FLOPS_PER_INTERACTION = 40
+# 3 sub (d), 3 FMA (s^2 + eps^2), 1 rsqrt, 1 sub (polynomial variable t),
+# 9 FMA (polynomial), 1 mul + 1 FMA (y^3 - H), 3 FMA (sum) = 38; boxes whose
+# masses differ add 1 mul (the source mass) = 39.  Compares and selects are
+# not counted; the compensated sum is amortised over 64-pair tiles.
+FLOPS_EQUAL_MASS = 38
+FLOPS_GENERAL = 39
 PAPER_FLOPS_PER_INTERACTION = 22      # convention of sec. 5 (Newtonian pair count)
 FP32_VECTOR_PEAK = 157.3e12           # MI355X, 256 CU x 2.4 GHz x 256 flop/clk
+# HBM bytes per PP-kernel launch on the headline workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by a plain 1 GiB copy measured the
+# same way (factors below).  Valid only for the kernel sources they were taken
+# on (SHA-1 over the files listed); otherwise the roofline reports null.
+TRAFFIC = {
+    "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
+                "paper_1802_09824_amd/csrc/pp_internal.h",
+                "paper_1802_09824_amd/csrc/tree.hip"],
+    "sha1": "276eaf7cf25eb4e8ad666b7f6c13de45929e9dba",
+    "fetch_bytes": 357314081,     # FETCH_SIZE 174475.3 KiB x 1.9999
+    "write_bytes": 116572304,     # WRITE_SIZE 113840.1 KiB x 1.0000
+    "fetch_scale": 1.9999,           # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
+    "write_scale": 1.0000,           # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
+}
+
+
+def sources_sha1(files):
+    import hashlib
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the PP kernel, or None if not measured for
+    the current kernel sources."""
+    t = TRAFFIC
+    if t["sha1"] is None or t["fetch_bytes"] is None:
+        return None
+    try:
+        if sources_sha1(t["sources"]) != t["sha1"]:
+            return None
+    except OSError:
+        return None
+    return float(t["fetch_bytes"] + t["write_bytes"])
 
 
 def parse():
@@ -43,6 +83,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-box batched-vs-per-box comparison")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the 64-box batched-vs-per-box comparison (for profiling)")
+    ap.add_argument("--print-sources-sha1", action="store_true",
+                    help="print the SHA-1 of the PP kernel sources the traffic figure is tied to")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference kernel "
                          "for scaling the HBM byte counters of a profiler run)")
@@ -91,7 +135,32 @@ def cpu_baseline(box, acc_gpu, budget_s):
     return base, errs
 
 
-def bench_batched(steps, warmup):
+def batched_error(boxes, acc_batched, per_box_targets=256, every=8):
+    """Errors of the batched result against the FP64 oracle on a seeded
+    sample of targets of every 8th box (the same tolerance as the plain path)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(1803)
+    off = np.cumsum([0] + [b.n for b in boxes])
+    es = []
+    for k in range(0, len(boxes), every):
+        b = boxes[k]
+        t = np.sort(rng.choice(b.n, min(b.n, per_box_targets), replace=False))
+        ref = oracle.accel(b.pos, b.mass.astype(np.float64), b.params, targets=t)
+        a = acc_batched[:, off[k] + t].astype(np.float64)
+        r = ref["acc"]
+        cands = [r, r - ref["band_in"] + ref["band_out"], r - ref["band_in"], r + ref["band_out"]]
+        err = np.min([np.linalg.norm(a - c, axis=0) for c in cands], axis=0)
+        norm = np.linalg.norm(r, axis=0)
+        has = ref["n_inter"] > 0
+        es.append(err[has] / norm[has])
+    e = np.concatenate(es) if es else np.zeros(0)
+    return {"boxes": len(range(0, len(boxes), every)), "targets": int(e.size),
+            "median": nearest_rank(e, 50), "p999": nearest_rank(e, 99.9),
+            "max": float(e.max()) if e.size else 0.0}
+
+
+def bench_batched(steps, warmup, with_error=True):
     """64 independent boxes (N uniform in 16^3..96^3, L in 50-300 Mpc/h,
     clustered fraction 0-0.8): one batched pp_batch_accel per step (all
     stages over all boxes, one persistent work-stealing PP launch replayed
@@ -121,6 +190,7 @@ def bench_batched(steps, warmup):
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / steps
     acc_batched = acc.cpu().numpy()
+    err = batched_error(boxes, acc_batched) if with_error else None
 
     # per box: separate inputs, plans and launches
     per = []
@@ -153,6 +223,7 @@ def bench_batched(steps, warmup):
         "speedup_whole_step": t_per / t_batched,
         "speedup_pp": (kernel_ms / steps) / float(np.mean(graph_ms)),
         "bit_identical_to_per_box": bool(same),
+        "error_vs_oracle": err,
         "unit": "interactions/s",
     }
 
@@ -169,6 +240,9 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
                           "repeats": 3}), flush=True)
         return
+    if args.print_sources_sha1:
+        print(sources_sha1(TRAFFIC["sources"]))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is a single-GPU "
               "kernel library and has no multi-GPU mode.", file=sys.stderr)
@@ -178,6 +252,10 @@ def main():
     import workloads
     import paper_1802_09824_amd as pp
 
+    if args.only_batched:
+        print(json.dumps({"batched_vs_per_box": bench_batched(max(1, min(args.steps, 5)), 1,
+                                                              with_error=False)}), flush=True)
+        return
     box = workloads.make_config(2)
     p = box.params
     pos = torch.tensor(box.pos, device="cuda")
@@ -201,7 +279,9 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     value = interactions * args.steps / elapsed
     k_ms = float(np.mean(kernel_ms))
-    achieved = interactions * FLOPS_PER_INTERACTION / (k_ms * 1e-3)
+    equal_mass = bool(np.all(box.mass == box.mass[0]))
+    flops = FLOPS_EQUAL_MASS if equal_mass else FLOPS_GENERAL
+    achieved = interactions * flops / (k_ms * 1e-3)
     out = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -211,9 +291,10 @@ def main():
                    "rcut": p.rcut, "eps": p.eps, "G": p.G, "leaf_max": p.leaf_max,
                    "clustered_fraction": 0.5, "spheres": 2000, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-                     "kernel": "pp_f32_kernel", "kernel_ms": k_ms,
-                     "flops_per_interaction": FLOPS_PER_INTERACTION},
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
+                     "kernel": "pp_f32_persistent", "kernel_ms": k_ms,
+                     "flops_per_interaction": flops},
         "interactions_per_step": interactions,
         "candidates_per_step": int(st["candidates"]),
         "evaluated_pairs_per_step": int(st["evaluated"]),
