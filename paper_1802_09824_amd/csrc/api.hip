@@ -190,10 +190,9 @@ struct Batch {
         if (mass_d) PP_TRY(w.mass_sd.reserve(8 * (N > 0 ? N : 1)));
         PP_TRY(stage_gather(bd, N, pos, mass_f, mass_d, w, s));
         if (mass_f) PP_TRY(stage_mass_flags(bd, N, w, s));
-        PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s));
         int bad = 0;
-        PP_HIP(hipMemcpyAsync(&bad, w.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-        PP_HIP(hipStreamSynchronize(s));
+        PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s,
+                            w.bad.as<int>(), &bad));
         if (bad) return fail(PP_EINVAL, "non-finite position or mass");
         PP_TRY(stage_trees(bd, w, s));
         PP_TRY(stage_lists(bd, poff, tune.chunk, w, s));

@@ -12,6 +12,7 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
 
 #include "pp_internal.h"
@@ -178,9 +179,21 @@ __global__ void __launch_bounds__(256) gather_keys_kernel(const uint64_t* __rest
     out[k] = keys[perm[k]];
 }
 
-struct to_i64 {
-    __device__ __host__ int64_t operator()(int32_t v) const { return (int64_t)v; }
+// i -> in[i] widened, 0 past the end: an exclusive scan over n + 1 of these
+// writes the offsets and the total (off[n]) in one pass.
+struct count_at {
+    const int32_t* in;
+    int64_t n;
+    __device__ __host__ int64_t operator()(int64_t i) const { return i < n ? (int64_t)in[i] : 0; }
 };
+using count_iter = rocprim::transform_iterator<rocprim::counting_iterator<int64_t>, count_at, int64_t>;
+
+// The key sort: one-sweep radix with 10-bit digits (7 passes over 63 key
+// bits instead of 8 with the library's 8-bit default for this target).
+using key_sort_config = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 8>, rocprim::kernel_config<1024, 8>,
+                                        10, rocprim::block_radix_rank_algorithm::match>>;
 
 }  // namespace
 
@@ -221,7 +234,7 @@ int launch_keys_raw(const double* pos, int64_t n, double L, int bits, uint64_t* 
 
 int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes) {
     size_t b = 0, b2 = 0;
-    PP_HIP(rocprim::radix_sort_pairs((void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+    PP_HIP(rocprim::radix_sort_pairs<key_sort_config>((void*)nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                      (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0,
                                      3 * bits, (hipStream_t)0));
     if (nbox > 1) {
@@ -238,7 +251,7 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
                     hipStream_t s) {
     if (n == 0) return PP_OK;
     size_t b = ws_bytes;
-    PP_HIP(rocprim::radix_sort_pairs(ws, b, keys, keys_out, idx_in, perm_out, (size_t)n, 0, 3 * bits,
+    PP_HIP(rocprim::radix_sort_pairs<key_sort_config>(ws, b, keys, keys_out, idx_in, perm_out, (size_t)n, 0, 3 * bits,
                                      s));
     return PP_OK;
 }
@@ -250,7 +263,7 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
     PP_TRY(w.sort_ws.reserve(need + 1));
     size_t b = w.sort_ws.bytes;
     if (bd.nbox <= 1) {
-        PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, w.keys.as<uint64_t>(),
+        PP_HIP(rocprim::radix_sort_pairs<key_sort_config>(w.sort_ws.p, b, w.keys.as<uint64_t>(),
                                          w.keys_s.as<uint64_t>(), w.iota.as<int32_t>(),
                                          w.perm.as<int32_t>(), (size_t)N, 0, 3 * bd.bits, s));
         return PP_OK;
@@ -262,7 +275,7 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
     uint16_t* box_a = w.sort_tmp.as<uint16_t>();
     uint16_t* box_b = box_a + N + 32;
     int32_t* idx1 = reinterpret_cast<int32_t*>(box_b + N + 32);
-    PP_HIP(rocprim::radix_sort_pairs(w.sort_ws.p, b, w.keys.as<uint64_t>(), w.keys_s.as<uint64_t>(),
+    PP_HIP(rocprim::radix_sort_pairs<key_sort_config>(w.sort_ws.p, b, w.keys.as<uint64_t>(), w.keys_s.as<uint64_t>(),
                                      w.iota.as<int32_t>(), idx1, (size_t)N, 0, 3 * bd.bits, s));
     hipLaunchKernelGGL(box_ids_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, idx1, N, box_a);
     PP_HIP(hipGetLastError());
@@ -292,9 +305,9 @@ int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* 
 
 int scan_workspace(int64_t n, size_t* bytes) {
     size_t b = 0;
-    rocprim::transform_iterator<const int32_t*, to_i64, int64_t> it((const int32_t*)nullptr, to_i64());
-    PP_HIP(rocprim::inclusive_scan((void*)nullptr, b, it, (int64_t*)nullptr, (size_t)n,
-                                   rocprim::plus<int64_t>(), (hipStream_t)0));
+    count_iter it(rocprim::counting_iterator<int64_t>(0), count_at{nullptr, n});
+    PP_HIP(rocprim::exclusive_scan((void*)nullptr, b, it, (int64_t*)nullptr, (int64_t)0,
+                                   (size_t)(n + 1), rocprim::plus<int64_t>(), (hipStream_t)0));
     *bytes = b;
     return PP_OK;
 }
@@ -306,13 +319,16 @@ int grow_scan(DevBuf& buf, int64_t n) {
 }
 
 int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s) {
-    hipLaunchKernelGGL(set_zero_i64, dim3(1), dim3(1), 0, s, off);
-    PP_HIP(hipGetLastError());
-    if (n == 0) return PP_OK;
+    if (n == 0) {
+        hipLaunchKernelGGL(set_zero_i64, dim3(1), dim3(1), 0, s, off);
+        PP_HIP(hipGetLastError());
+        return PP_OK;
+    }
     PP_TRY(grow_scan(ws, n));
     size_t b = ws.bytes;
-    rocprim::transform_iterator<const int32_t*, to_i64, int64_t> it(in, to_i64());
-    PP_HIP(rocprim::inclusive_scan(ws.p, b, it, off + 1, (size_t)n, rocprim::plus<int64_t>(), s));
+    count_iter it(rocprim::counting_iterator<int64_t>(0), count_at{in, n});
+    PP_HIP(rocprim::exclusive_scan(ws.p, b, it, off, (int64_t)0, (size_t)(n + 1),
+                                   rocprim::plus<int64_t>(), s));
     return PP_OK;
 }
 

@@ -182,8 +182,10 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
                     hipStream_t s);
 
 // tree.hip  (positions passed here are wrapped: x - L floor(x / L))
+// Leaves of every box.  Synchronises the stream once; when bad_dev is given
+// the int it points to is read back into *bad_host in the same transfer.
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
-                 Work& w, hipStream_t s);
+                 Work& w, hipStream_t s, const int* bad_dev = nullptr, int* bad_host = nullptr);
 int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
                 hipStream_t s);

@@ -425,7 +425,26 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
         if (l >= ia.bcount[b]) continue;
         if (ia.ioff[b + 1] - ia.ioff[b] == 1) continue;     // written by the PP kernel
         double sx = 0, sy = 0, sz = 0;
-        for (int64_t it = ia.ioff[b]; it < ia.ioff[b + 1]; ++it) {
+        const int64_t end = ia.ioff[b + 1];
+        int64_t it = ia.ioff[b];
+        // four items' loads in flight at once; the sums keep item order
+        for (; it + 4 <= end; it += 4) {
+            float v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float* o = partial + (it + u) * 3 * kBlock;
+                v[u][0] = o[0 * kBlock + l];
+                v[u][1] = o[1 * kBlock + l];
+                v[u][2] = o[2 * kBlock + l];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sx += (double)v[u][0];
+                sy += (double)v[u][1];
+                sz += (double)v[u][2];
+            }
+        }
+        for (; it < end; ++it) {
             const float* o = partial + it * 3 * kBlock;
             sx += (double)o[0 * kBlock + l];
             sy += (double)o[1 * kBlock + l];

@@ -139,18 +139,25 @@ __global__ void leaf_box_kernel(BatchDev bd, const double* __restrict__ pos_s, i
 }
 
 // First leaf of every box: the first leaf starting at or after poff[x].
-__global__ void leaf_offsets_kernel(BatchDev bd, const int64_t* __restrict__ begin, int64_t m,
+// First leaf of every box (and the leaf total at x = nbox): every box start
+// starts a leaf, so the leaves before box x are the leaf starts before its
+// first particle, the exclusive flag scan at that index.
+__global__ void leaf_offsets_kernel(BatchDev bd, const int64_t* __restrict__ flag_off,
                                     int64_t* __restrict__ loff) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x > bd.nbox) return;
-    const int64_t p = bd.poff[x];
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (begin[mid] < p) lo = mid + 1;
-        else hi = mid;
-    }
-    loff[x] = lo;
+    loff[x] = flag_off[bd.poff[x]];
+}
+
+// Sizes read from device memory by the graph-captured kernels.
+__global__ void set_sizes_kernel(int64_t* __restrict__ sizes, int64_t nblock, int64_t nitem,
+                                 int64_t nrange, int64_t nentry) {
+    if (threadIdx.x != 0) return;
+    sizes[0] = nblock;
+    sizes[1] = nitem;
+    sizes[2] = nrange;
+    sizes[3] = nentry;
+    for (int k = 4; k < 8; ++k) sizes[k] = 0;
 }
 
 // Level h >= 1 of every box's tree: node i of box x is the union of its
@@ -713,7 +720,7 @@ __global__ void item_fill_kernel(const int32_t* __restrict__ icount,
 }  // namespace
 
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
-                 Work& w, hipStream_t s) {
+                 Work& w, hipStream_t s, const int* bad_dev, int* bad_host) {
     w.nleaf = 0;
     w.loff.assign(bd.nbox + 1, 0);
     if (N == 0) return PP_OK;
@@ -736,26 +743,29 @@ int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, con
                        w.level_p.as<int8_t>(), N, w.flag.as<int32_t>());
     PP_HIP(hipGetLastError());
     PP_TRY(launch_scan_i32_to_i64(w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N, w.scan_ws, s));
-    int64_t m = 0;
-    PP_TRY(read_back(w.flag_off.as<int64_t>() + N, &m, s));
+    PP_TRY(w.loff_dev.reserve(sizeof(int64_t) * (bd.nbox + 1)));
+    hipLaunchKernelGGL(leaf_offsets_kernel, dim3(blocks_for(bd.nbox + 1, 64)), dim3(64), 0, s, bd,
+                       w.flag_off.as<int64_t>(), w.loff_dev.as<int64_t>());
+    PP_HIP(hipGetLastError());
+    // one read-back: the per-box leaf offsets (total at the end) and, when
+    // asked, the input-check flag
+    PP_HIP(hipMemcpyAsync(w.loff.data(), w.loff_dev.p, sizeof(int64_t) * (bd.nbox + 1),
+                          hipMemcpyDeviceToHost, s));
+    if (bad_dev) PP_HIP(hipMemcpyAsync(bad_host, bad_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    const int64_t m = w.loff[bd.nbox];
     PP_TRY(w.lbegin.reserve(sizeof(int64_t) * (m + 1)));
     PP_TRY(w.lcount.reserve(sizeof(int32_t) * (m + 1)));
     PP_TRY(w.llevel.reserve(sizeof(int32_t) * (m + 1)));
     PP_TRY(w.lprefix.reserve(sizeof(uint64_t) * (m + 1)));
     PP_TRY(w.lboxes.reserve(sizeof(IBox) * (m + 1)));
-    PP_TRY(w.loff_dev.reserve(sizeof(int64_t) * (bd.nbox + 1)));
     hipLaunchKernelGGL(leaf_fill_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, sorted_keys,
                        w.level_p.as<int8_t>(), w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N,
                        bd.bits, w.lbegin.as<int64_t>(), w.llevel.as<int32_t>(),
                        w.lprefix.as<uint64_t>());
     hipLaunchKernelGGL(leaf_box_kernel, dim3(blocks_for(m, 128)), dim3(128), 0, s, bd, pos_s, N,
                        w.lbegin.as<int64_t>(), m, w.lcount.as<int32_t>(), w.lboxes.as<IBox>());
-    hipLaunchKernelGGL(leaf_offsets_kernel, dim3(blocks_for(bd.nbox + 1, 64)), dim3(64), 0, s, bd,
-                       w.lbegin.as<int64_t>(), m, w.loff_dev.as<int64_t>());
     PP_HIP(hipGetLastError());
-    PP_HIP(hipMemcpyAsync(w.loff.data(), w.loff_dev.p, sizeof(int64_t) * (bd.nbox + 1),
-                          hipMemcpyDeviceToHost, s));
-    PP_HIP(hipStreamSynchronize(s));
     w.nleaf = m;
     return PP_OK;
 }
@@ -1012,9 +1022,9 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_HIP(hipGetLastError());
     // sizes read by graph-captured kernels
     PP_TRY(w.sizes.reserve(sizeof(int64_t) * 8));
-    const int64_t sz[8] = {w.nblock, w.nitem, w.nrange, w.nentry, 0, 0, 0, 0};
-    PP_HIP(hipMemcpyAsync(w.sizes.p, sz, sizeof(sz), hipMemcpyHostToDevice, s));
-    PP_HIP(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(set_sizes_kernel, dim3(1), dim3(64), 0, s, w.sizes.as<int64_t>(), w.nblock,
+                       w.nitem, w.nrange, w.nentry);
+    PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
