@@ -118,6 +118,16 @@ def cpu_baseline(box, acc_gpu, budget_s):
     ref = oracle.accel(box.pos, mass64, box.params, targets=targets)
     sec = time.perf_counter() - t0
     inter = int(ref["n_inter"].sum())
+    base = {"value": inter / sec, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{k} seeded random targets of the same box against all {box.n} sources "
+                      f"(FP64 direct sum, {inter} interactions, {sec:.1f} s)"}
+    return base, sample_errors(acc_gpu, targets, ref), targets, ref
+
+
+def sample_errors(acc_gpu, targets, ref):
+    """Band-tolerant relative errors of GPU accelerations on oracle targets."""
+    import numpy as np
     a = acc_gpu[:, targets].astype(np.float64)
     r = ref["acc"]
     cands = [r, r - ref["band_in"] + ref["band_out"], r - ref["band_in"], r + ref["band_out"]]
@@ -125,14 +135,9 @@ def cpu_baseline(box, acc_gpu, budget_s):
     norm = np.linalg.norm(r, axis=0)
     has = ref["n_inter"] > 0
     e = err[has] / norm[has]
-    base = {"value": inter / sec, "unit": "interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{k} seeded random targets of the same box against all {box.n} sources "
-                      f"(FP64 direct sum, {inter} interactions, {sec:.1f} s)"}
-    errs = {"targets": int(has.sum()), "median": nearest_rank(e, 50), "p999": nearest_rank(e, 99.9),
+    return {"targets": int(has.sum()), "median": nearest_rank(e, 50), "p999": nearest_rank(e, 99.9),
             "max": float(e.max()) if e.size else 0.0,
             "zero_neighbour_exact": bool(np.all(a[:, ~has] == 0))}
-    return base, errs
 
 
 def batched_error(boxes, acc_batched, per_box_targets=256, every=8):
@@ -304,9 +309,24 @@ def main():
         "lists": {k: int(st[k]) for k in ("nleaf", "nblock", "nrange", "nitem")},
     }
     if not args.no_cpu_baseline:
-        base, errs = cpu_baseline(box, acc.cpu().numpy(), args.cpu_seconds)
+        base, errs, targets, ref = cpu_baseline(box, acc.cpu().numpy(), args.cpu_seconds)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = errs
+        # the split factor from the interpolated LDS table (variant 8)
+        # instead of the polynomial: same lists, same steps
+        plan.set_tuning(variant=8)
+        for _ in range(2):
+            plan.accel(pos, mass, out=acc)
+        tab_ms = []
+        for _ in range(max(3, min(args.steps, 10))):
+            plan.accel(pos, mass, out=acc)
+            tab_ms.append(plan.stats()["pp_kernel_ms"])
+        t_ms = float(np.mean(tab_ms))
+        out["split_table_variant"] = {
+            "kernel_ms": t_ms, "pp_kernel_interactions_per_s": interactions / (t_ms * 1e-3),
+            "vs_polynomial_kernel": k_ms / t_ms,
+            "error_vs_oracle": sample_errors(acc.cpu().numpy(), targets, ref)}
+        plan.set_tuning(variant=0)
     if not args.no_batched:
         del plan, pos, mass, acc
         torch.cuda.empty_cache()

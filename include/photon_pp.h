@@ -184,11 +184,14 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *  waves_per_cu used by the persistent form, 1..64
  *  use_graph    1: capture the persistent kernel and the reduction in a
  *               hipGraph once and replay it (needs persistent = 1)
- *  variant      arithmetic ablations for precision studies (bit flags):
- *               1 = one Newton step after the hardware rsqrt, 2 = no Kahan
- *               compensation of the per-target sums, 4 = offsets from the
- *               box origin instead of the FP64 block centre.  0 is the
- *               production kernel.
+ *  variant      arithmetic variants (bit flags): 1 = one Newton step after
+ *               the hardware rsqrt, 2 = no Kahan compensation of the
+ *               per-target sums, 4 = offsets from the box origin instead of
+ *               the FP64 block centre (these three are precision
+ *               ablations), 8 = the split factor from an interpolated
+ *               table in LDS (128 quadratic pieces, the form sec. 3.1
+ *               describes) instead of the polynomial.  0 is the production
+ *               kernel.
  *  groups       reserved, must be 1 (sources are pruned against the
  *               target block's bounding box).
  * The chunk grows by itself when the lists are long enough that more than

@@ -113,6 +113,7 @@ struct Batch {
     Work w;
     pp_tuning tune{2048, 1, 20, 0, 0, 1};
     int64_t graph_variant = -1;
+    bool table_ready = false;      // the interpolated split table is built
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
     bool timing = false, timed = false;
@@ -190,6 +191,10 @@ struct Batch {
         if (mass_d) PP_TRY(w.mass_sd.reserve(8 * (N > 0 ? N : 1)));
         PP_TRY(stage_gather(bd, N, pos, mass_f, mass_d, w, s));
         if (mass_f) PP_TRY(stage_mass_flags(bd, N, w, s));
+        if (mass_f && !table_ready) {
+            PP_TRY(launch_split_table(w, s));
+            table_ready = true;
+        }
         int bad = 0;
         PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s,
                             w.bad.as<int>(), &bad));
@@ -397,7 +402,7 @@ struct Batch {
     static bool check_tuning_ok(const pp_tuning& t) {
         return t.chunk >= 64 && t.chunk <= (1 << 24) && t.chunk % 64 == 0 && t.waves_per_cu >= 1 &&
                t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
-               t.variant <= 7 && t.groups == 1;
+               t.variant <= 15 && t.groups == 1;
     }
 
     int set_timing(int on) {
@@ -417,7 +422,7 @@ static int check_tuning(const pp_tuning* t) {
         return fail(PP_EINVAL, "chunk must be a multiple of 64 in 64..2^24");
     if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
     if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
-    if (t->variant < 0 || t->variant > 7) return fail(PP_EINVAL, "variant must be in 0..7");
+    if (t->variant < 0 || t->variant > 15) return fail(PP_EINVAL, "variant must be in 0..15");
     if (t->groups != 1) return fail(PP_EINVAL, "groups must be 1");
     return PP_OK;
 }

@@ -136,6 +136,7 @@ struct Work {
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
     DevBuf mass_flag;        // int32 [nbox]: 1 where the box's FP32 masses are not all equal
+    DevBuf split_tab;        // float4 [128]: the interpolated split table (variant bit 8)
     DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
     DevBuf lam, pmax, smax, level_p, flag, flag_off;
@@ -210,6 +211,8 @@ int launch_reduce_f64(const BatchDev& bd, const Work& w, const double* partial, 
 int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial, hipStream_t s);
 int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partial, int64_t* counts,
                         unsigned long long* total, hipStream_t s);
+// Builds the interpolated split table (FP64 series, rounded to FP32).
+int launch_split_table(Work& w, hipStream_t s);
 int launch_reset_queues(unsigned* queues, hipStream_t s);
 
 }  // namespace pp

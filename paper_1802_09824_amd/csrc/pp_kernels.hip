@@ -47,6 +47,7 @@ struct ItemArgs {
     const BoxDev* box;
     const int32_t* perm;       // key order -> input order
     const int32_t* mass_flag;  // per box: 1 where the masses are not all equal
+    const float4* split_tab;   // the interpolated split table (variant bit 8)
     float* acc;                // FP32 output (single-item blocks write it directly)
     int chunk;
 };
@@ -69,6 +70,7 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.box = bd.box;
     ia.perm = w.perm.as<int32_t>();
     ia.mass_flag = w.mass_flag.as<int32_t>();
+    ia.split_tab = w.split_tab.as<float4>();
     ia.acc = nullptr;
     ia.chunk = w.chunk;       // the effective chunk the items were cut with
     return ia;
@@ -102,16 +104,23 @@ constexpr double kHScale = 0.5 * SPLIT_POLY_U_MAX * csqrt(0.5 * SPLIT_POLY_U_MAX
 static_assert(SPLIT_POLY_DEGREE == 9, "the pair function unrolls a degree-9 polynomial");
 #define PP_HC(j) ((float)(kHScale * SPLIT_POLY_C[j]))
 
-// One source against the lane's target; adds into (tx, ty, tz).
-template <bool NEWTON>
-__device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, float zi,
-                                         const PolyF32& P, float& tx, float& ty, float& tz) {
-    const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
-    float r2 = fmaf(dx, dx, P.eps2n);
-    r2 = fmaf(dy, dy, r2);
-    r2 = fmaf(dz, dz, r2);
-    float y = __builtin_amdgcn_rsqf(r2);
-    if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+// (U_max/2)^{3/2} H(u) at r2 = s_eps^2 / ell^2: the degree-9 polynomial in
+// t = r2 - 1, or (TABLE) the interpolated table of the paper's design: kTabN
+// quadratic pieces over r2 in [0, 2), each stored as (a, b, c) with
+// h = a + z (b + z c), z the position inside the piece.  Past r2 = 2 the
+// last piece is extrapolated; such pairs lie beyond the cut and are masked.
+constexpr int kTabN = 128;
+
+template <bool TABLE>
+__device__ __forceinline__ float split_h(float r2, const float4* __restrict__ tab) {
+    if (TABLE) {
+        const float sidx = r2 * (float)(kTabN / 2);
+        int k = (int)sidx;
+        k = k < kTabN - 1 ? k : kTabN - 1;
+        const float z = sidx - (float)k;
+        const float4 c = tab[k];
+        return fmaf(fmaf(c.z, z, c.y), z, c.x);
+    }
     const float t = r2 - 1.f;
     float h = fmaf(t, PP_HC(9), PP_HC(8));
     h = fmaf(h, t, PP_HC(7));
@@ -121,7 +130,21 @@ __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, fl
     h = fmaf(h, t, PP_HC(3));
     h = fmaf(h, t, PP_HC(2));
     h = fmaf(h, t, PP_HC(1));
-    h = fmaf(h, t, PP_HC(0));
+    return fmaf(h, t, PP_HC(0));
+}
+
+// One source against the lane's target; adds into (tx, ty, tz).
+template <bool NEWTON, bool TABLE = false>
+__device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, float zi,
+                                         const PolyF32& P, float& tx, float& ty, float& tz,
+                                         const float4* __restrict__ tab = nullptr) {
+    const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
+    float r2 = fmaf(dx, dx, P.eps2n);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    float y = __builtin_amdgcn_rsqf(r2);
+    if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float h = split_h<TABLE>(r2, tab);
     const float y3 = y * y * y;
     float F = (y3 - h) * sj.w;
     F = r2 < P.cut2 ? F : 0.f;
@@ -133,25 +156,17 @@ __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, fl
 // The same for a box whose masses are all equal: the source's w slot holds
 // the cut on r2 instead of the mass (which joins the final scale), so the
 // tile keeps its 16-byte entries and the mass multiply drops out.
-template <bool NEWTON>
+template <bool NEWTON, bool TABLE = false>
 __device__ __forceinline__ void pair_f32_eq(const float4 sj, float xi, float yi, float zi,
-                                            float& tx, float& ty, float& tz, float eps2) {
+                                            float& tx, float& ty, float& tz, float eps2,
+                                            const float4* __restrict__ tab = nullptr) {
     const float dx = sj.x - xi, dy = sj.y - yi, dz = sj.z - zi;
     float r2 = fmaf(dx, dx, eps2);
     r2 = fmaf(dy, dy, r2);
     r2 = fmaf(dz, dz, r2);
     float y = __builtin_amdgcn_rsqf(r2);
     if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
-    const float t = r2 - 1.f;
-    float h = fmaf(t, PP_HC(9), PP_HC(8));
-    h = fmaf(h, t, PP_HC(7));
-    h = fmaf(h, t, PP_HC(6));
-    h = fmaf(h, t, PP_HC(5));
-    h = fmaf(h, t, PP_HC(4));
-    h = fmaf(h, t, PP_HC(3));
-    h = fmaf(h, t, PP_HC(2));
-    h = fmaf(h, t, PP_HC(1));
-    h = fmaf(h, t, PP_HC(0));
+    const float h = split_h<TABLE>(r2, tab);
     const float y3 = y * y * y;
     float F = y3 - h;
     F = r2 < sj.w ? F : 0.f;
@@ -202,10 +217,12 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
                                         const double* __restrict__ pos_s,
                                         const float* __restrict__ mass_s, int64_t N,
                                         float* __restrict__ partial,
-                                        unsigned long long* __restrict__ counters, float4* tile) {
+                                        unsigned long long* __restrict__ counters, float4* tile,
+                                        const float4* __restrict__ tab) {
     constexpr bool NEWTON = (VAR & 1) != 0;
     constexpr bool KAHAN = (VAR & 2) == 0;
     constexpr bool LOCAL = (VAR & 4) == 0;     // FP64 block-centre subtraction
+    constexpr bool TABLE = (VAR & 8) != 0;     // interpolated split table
     const int lane = threadIdx.x;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];
@@ -304,17 +321,17 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
                 if (equal) {
 #pragma unroll 8
                     for (int q = 0; q < kBlock; ++q)
-                        pair_f32_eq<NEWTON>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n);
+                        pair_f32_eq<NEWTON, TABLE>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n, tab);
                 } else {
 #pragma unroll 8
-                    for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+                    for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON, TABLE>(tile[q], xi, yi, zi, P, tx, ty, tz, tab);
                 }
                 kahan_add(ax, cx, tx);
                 kahan_add(ay, cy, ty);
                 kahan_add(az, cz, tz);
             } else {
 #pragma unroll 8
-                for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, ax, ay, az);
+                for (int q = 0; q < kBlock; ++q) pair_f32<NEWTON, TABLE>(tile[q], xi, yi, zi, P, ax, ay, az, tab);
             }
             wave_sync();
             count -= kBlock;
@@ -327,15 +344,15 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         float tx = 0.f, ty = 0.f, tz = 0.f;
         if (KAHAN) {
             if (equal) {
-                for (int q = 0; q < count; ++q) pair_f32_eq<NEWTON>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n);
+                for (int q = 0; q < count; ++q) pair_f32_eq<NEWTON, TABLE>(tile[q], xi, yi, zi, tx, ty, tz, P.eps2n, tab);
             } else {
-                for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, tx, ty, tz);
+                for (int q = 0; q < count; ++q) pair_f32<NEWTON, TABLE>(tile[q], xi, yi, zi, P, tx, ty, tz, tab);
             }
             kahan_add(ax, cx, tx);
             kahan_add(ay, cy, ty);
             kahan_add(az, cz, tz);
         } else {
-            for (int q = 0; q < count; ++q) pair_f32<NEWTON>(tile[q], xi, yi, zi, P, ax, ay, az);
+            for (int q = 0; q < count; ++q) pair_f32<NEWTON, TABLE>(tile[q], xi, yi, zi, P, ax, ay, az, tab);
         }
     }
     if (counters && lane == 0) {
@@ -370,9 +387,14 @@ __global__ void __launch_bounds__(64, 6) pp_f32_kernel(ItemArgs ia, const double
                                                     int64_t per_xcd, float* __restrict__ partial,
                                                     unsigned long long* __restrict__ counters) {
     __shared__ float4 tile[2 * kBlock];
+    __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
     const int64_t item = xcd_item(blockIdx.x, per_xcd);
     if (item >= ia.sizes[1]) return;
-    pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile);
+    if (VAR & 8) {
+        for (int k = threadIdx.x; k < kTabN; k += kBlock) tab[k] = ia.split_tab[k];
+        __syncthreads();
+    }
+    pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab);
 }
 
 // Persistent form: a fixed grid of waves pulls items from 8 queues (one
@@ -388,6 +410,11 @@ __global__ void __launch_bounds__(64, 6) pp_f32_persistent(ItemArgs ia,
                                                         unsigned long long* __restrict__ counters,
                                                         unsigned* __restrict__ queues) {
     __shared__ float4 tile[2 * kBlock];
+    __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
+    if (VAR & 8) {
+        for (int k = threadIdx.x; k < kTabN; k += kBlock) tab[k] = ia.split_tab[k];
+        __syncthreads();
+    }
     const int64_t nitem = ia.sizes[1];
     const int64_t per = (nitem + 7) / 8;
     const int my = blockIdx.x & 7;
@@ -402,7 +429,7 @@ __global__ void __launch_bounds__(64, 6) pp_f32_persistent(ItemArgs ia,
             i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
             const int64_t item = qbeg + (int64_t)i;
             if (item >= qend) break;
-            pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile);
+            pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab);
         }
     }
 }
@@ -605,6 +632,41 @@ int make_poly(const pp_box_params& p, PolyF32* out) {
     return PP_OK;
 }
 
+// H(u) = (1 - g(x)) / x^3, u = x^2, from g'(x) = -(4/sqrt(pi)) x^2 e^{-x^2}:
+// 1 - g(x) = (4/sqrt(pi)) sum_n (-1)^n x^{2n+3} / (n! (2n+3)), so
+// H(u) = (4/sqrt(pi)) sum_n (-u)^n / (n! (2n+3)).  In FP64 the alternating
+// terms stay below 40 for u <= 5.2, so the sum keeps about 14 digits.
+__device__ double split_H_series(double u) {
+    double term = 1.0, sum = 1.0 / 3.0;
+    for (int n = 1; n < 80; ++n) {
+        term *= -u / (double)n;
+        sum += term / (double)(2 * n + 3);
+        if (fabs(term) < 1e-18) break;
+    }
+    return 4.0 / 1.7724538509055160272981674833411 * sum;
+}
+
+// Piece k of the table covers r2 in [2k/N, 2(k+1)/N); the quadratic through
+// the piece's two ends and midpoint, in z = position inside the piece.
+__global__ void split_table_kernel(float4* __restrict__ tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kTabN) return;
+    const double hu = 0.5 * SPLIT_POLY_U_MAX;           // u per unit of r2
+    const double w = 2.0 / kTabN;
+    const double f0 = kHScale * split_H_series(hu * (k * w));
+    const double fm = kHScale * split_H_series(hu * ((k + 0.5) * w));
+    const double f1 = kHScale * split_H_series(hu * ((k + 1) * w));
+    tab[k] = make_float4((float)f0, (float)(-3.0 * f0 + 4.0 * fm - f1), (float)(2.0 * f0 - 4.0 * fm + 2.0 * f1),
+                         0.f);
+}
+
+int launch_split_table(Work& w, hipStream_t s) {
+    PP_TRY(w.split_tab.reserve(sizeof(float4) * kTabN));
+    hipLaunchKernelGGL(split_table_kernel, dim3(1), dim3(kTabN), 0, s, w.split_tab.as<float4>());
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
 int launch_reset_queues(unsigned* queues, hipStream_t s) {
     hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, queues);
     PP_HIP(hipGetLastError());
@@ -640,7 +702,7 @@ int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int 
     (void)groups;
     ItemArgs ia = item_args(bd, w, 0);
     ia.acc = acc;
-    switch (variant & 7) {
+    switch (variant & 15) {
         case 0: return launch_pp_f32_var<0>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 1: return launch_pp_f32_var<1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 2: return launch_pp_f32_var<2>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
@@ -648,7 +710,15 @@ int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int 
         case 4: return launch_pp_f32_var<4>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 5: return launch_pp_f32_var<5>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 6: return launch_pp_f32_var<6>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        default: return launch_pp_f32_var<7>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 7: return launch_pp_f32_var<7>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 8: return launch_pp_f32_var<8>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 9: return launch_pp_f32_var<9>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 10: return launch_pp_f32_var<10>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 11: return launch_pp_f32_var<11>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 12: return launch_pp_f32_var<12>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 13: return launch_pp_f32_var<13>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 14: return launch_pp_f32_var<14>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        default: return launch_pp_f32_var<15>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
     }
 }
 

@@ -241,3 +241,58 @@ def test_accel_f32_cfg2_sampled(pp, cfg2_sample):
     assert s["median"] <= 1e-6 and s["p999"] <= 1e-4
     tot, counts = plan.count_interactions(per_target=True)
     assert np.array_equal(counts.cpu().numpy()[targets], ref["n_inter"])
+
+
+def test_fp32_momentum_and_translation(pp, oracle_mod):
+    """Pairwise antisymmetry gives sum_i m_i a_i = 0; the FP32 kernel keeps it
+    to FP32 rounding.  Shifting every position by a constant (mod L) moves
+    keys, leaves and blocks but not the forces."""
+    b = W.make_config(1)
+    m = b.mass.astype(np.float64)
+    plan = pp.Plan(b.params, b.n)
+    acc = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy().astype(np.float64)
+    net = np.linalg.norm((acc * m).sum(axis=1))
+    scale = (np.linalg.norm(acc, axis=0) * m).sum()
+    print("FP32 |sum m a| / sum m |a| =", net / scale)
+    assert net / scale <= 1e-5
+    shifted = np.mod(b.pos + np.array([[13.7], [-41.25], [77.03125]]), b.params.L)
+    acc2 = plan.accel(dev(shifted, torch.float64), dev(b.mass, torch.float32)).cpu().numpy().astype(np.float64)
+    ref = oracle_mod.accel(b.pos, m, b.params)
+    s1 = parity.summary(acc.astype(np.float32), ref)
+    s2 = parity.summary(acc2.astype(np.float32), ref)
+    assert s2["median"] <= 1e-6 and s2["p999"] <= 1e-4, s2
+    rel = np.linalg.norm(acc2 - acc, axis=0) / np.maximum(np.linalg.norm(ref["acc"], axis=0), 1e-300)
+    assert np.median(rel) <= 2e-6, (np.median(rel), s1, s2)
+
+
+TABLE_CASES = ["n1", "n2-across-boundary", "n65", "ragged-3000", "coincident-eps0", "wide-cut",
+               "edge-wrap", "leaf1024"]
+
+
+@pytest.mark.parametrize("case", [c for c in TABLE_CASES if c in EDGE_CASES])
+@pytest.mark.parametrize("equal", [False, True])
+def test_split_table_variant_edge_cases(pp, oracle_mod, case, equal):
+    """Variant 8 takes the split factor from the interpolated LDS table (the
+    form of sec. 3.1) instead of the polynomial; same tolerance."""
+    pos, p = EDGE_CASES[case]()
+    n = pos.shape[1]
+    mass = np.random.default_rng(n).uniform(0.5, 1.5, n).astype(np.float32)
+    if equal:
+        mass[:] = np.float32(1.0 / n)
+    ref = oracle_mod.accel(pos, mass.astype(np.float64), p)
+    plan = pp.Plan(p, n + 10)
+    plan.set_tuning(variant=8)
+    acc = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    s = parity.summary(acc, ref)
+    assert s["zero_ok"], case
+    assert s["median"] <= 1e-6 and s["p999"] <= 1e-4, (case, s)
+
+
+def test_split_table_variant_cfg2_sampled(pp, cfg2_sample):
+    b, targets, ref = cfg2_sample
+    plan = pp.Plan(b.params, b.n)
+    plan.set_tuning(variant=8)
+    acc = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()[:, targets]
+    s = parity.summary(acc, ref)
+    print("cfg2 split-table variant sampled", s)
+    assert s["median"] <= 1e-6 and s["p999"] <= 1e-4
