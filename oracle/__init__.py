@@ -8,7 +8,8 @@ The arithmetic lives in pp_oracle.c (plain C, FP64); this module only
 marshals numpy arrays.  Function-by-function citations are in that file:
 split factor (sec. 3.1, Eq. equ:split), direct short-range sum (sec. 3.1
 r_cut = 4.5 r_s; sec. 3.3 N-to-M PP), Peano-Hilbert keys (sec. 4.1),
-octree leaves (sec. 3.2-3.3), near leaf pairs (sec. 3.3).
+octree leaves (sec. 3.2-3.3), near leaf pairs (sec. 3.3).  The long-range
+PM force (sec. 3.1) is plain numpy in pm.py.
 """
 from __future__ import annotations
 
