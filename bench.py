@@ -165,6 +165,39 @@ def batched_error(boxes, acc_batched, per_box_targets=256, every=8):
             "max": float(e.max()) if e.size else 0.0}
 
 
+def bench_pm(box, pos, mass, n_mesh, steps, with_error=True):
+    """The long-range PM force of the same box (pp_pm_accel): CIC, FFTs,
+    Green function with the Gaussian filter, gradient, interpolation.
+    Timed with events on the stream the library launches on."""
+    import numpy as np
+    import torch
+    import paper_1802_09824_amd as pp
+    plan = pp.PMPlan(box.params, n_mesh)
+    acc = torch.empty((3, box.n), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        plan.accel(pos, mass, out=acc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.accel(pos, mass, out=acc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"n_mesh": n_mesh, "ms_per_call": ms, "particles_per_s": box.n / (ms * 1e-3)}
+    if with_error:
+        from oracle import pm as opm
+        ref = opm.pm_accel(box.pos, box.mass.astype(np.float64), box.params, n_mesh)
+        a = acc.cpu().numpy().astype(np.float64)
+        mag = np.linalg.norm(ref, axis=0)
+        floor = 1e-6 * np.sqrt(np.mean(mag ** 2))
+        e = np.linalg.norm(a - ref, axis=0) / np.maximum(mag, floor)
+        res["error_vs_oracle"] = {"particles": int(box.n), "median": nearest_rank(e, 50),
+                                  "p999": nearest_rank(e, 99.9), "max": float(e.max())}
+    del plan
+    return res
+
+
 def bench_batched(steps, warmup, with_error=True):
     """64 independent boxes (N uniform in 16^3..96^3, L in 50-300 Mpc/h,
     clustered fraction 0-0.8): one batched pp_batch_accel per step (all
@@ -327,6 +360,8 @@ def main():
             "vs_polynomial_kernel": k_ms / t_ms,
             "error_vs_oracle": sample_errors(acc.cpu().numpy(), targets, ref)}
         plan.set_tuning(variant=0)
+    out["pm_long_range"] = bench_pm(box, pos, mass, 128, max(3, min(args.steps, 10)),
+                                    with_error=not args.no_cpu_baseline)
     if not args.no_batched:
         del plan, pos, mass, acc
         torch.cuda.empty_cache()

@@ -244,6 +244,33 @@ int pp_batch_set_tuning(pp_batch_plan* bp, const pp_tuning* t);
 int pp_batch_autotune(pp_batch_plan* bp, const double* pos, const float* mass,
                       const char* cache_path, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Long-range force: particle-mesh (sec. 3.1)
+ * ---------------------------------------------------------------------
+ * The PM half of the force split of Eq. equ:split, on one periodic box:
+ * cloud-in-cell assignment of the masses to an n_mesh^3 mesh; a forward
+ * FFT; the 3-point difference Green function of sec. 3.1,
+ *   phi_k = -pi G Delta^2 rho_k / (sin^2(pi l/N) + sin^2(pi m/N) + sin^2(pi n/N)),
+ * times the long-range filter exp(-k^2 r_s^2) (k = 0 dropped); an inverse
+ * FFT; -grad phi by a 4-point central difference; linear (CIC)
+ * interpolation to the particles.  Mesh arithmetic is FP64 (the FFTs by
+ * hipFFT); the output is FP32.  pp_accel + pp_pm_accel is the whole force.
+ * The mass assignment adds with FP64 atomics, so repeated calls can differ
+ * in the last FP64 bits before the FP32 rounding.
+ *
+ * pp_pm_plan_create: p gives L, rs (the filter scale) and G (rcut, eps,
+ *   leaf_max and key_bits are validated but unused); 4 <= n_mesh <= 2048.
+ *   The plan owns its meshes (about 56 n_mesh^3 bytes) and FFT plans.
+ * pp_pm_accel: pos SoA FP64 [3][n] (any real values, wrapped into [0, L)),
+ *   mass FP32 [n], acc FP32 [3][n] written (not added); device pointers,
+ *   enqueued on the stream.  Non-finite positions are placed at the origin
+ *   (they are not detected here; pp_accel reports them). */
+typedef struct pp_pm_plan pp_pm_plan;
+int pp_pm_plan_create(const pp_box_params* p, int32_t n_mesh, pp_pm_plan** out);
+int pp_pm_accel(pp_pm_plan* plan, const double* pos, const float* mass, int64_t n, float* acc,
+                void* stream);
+void pp_pm_plan_destroy(pp_pm_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

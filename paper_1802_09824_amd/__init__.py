@@ -85,6 +85,9 @@ _SIGS = {
     "pp_batch_set_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
     "pp_autotune": (_i32, [_P, _P, _P, _i64, C.c_char_p, _P]),
     "pp_batch_autotune": (_i32, [_P, _P, _P, C.c_char_p, _P]),
+    "pp_pm_plan_create": (_i32, [C.POINTER(pp_box_params), _i32, C.POINTER(_P)]),
+    "pp_pm_accel": (_i32, [_P, _P, _P, _i64, _P, _P]),
+    "pp_pm_plan_destroy": (None, [_P]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -360,3 +363,36 @@ class BatchPlan:
 
 def pp_batch_plan_create(params_list, ns) -> BatchPlan:
     return BatchPlan(params_list, ns)
+
+
+class PMPlan:
+    """Long-range particle-mesh force of one periodic box (pp_pm_*)."""
+
+    def __init__(self, params, n_mesh: int):
+        self.params = params
+        self.n_mesh = int(n_mesh)
+        h = C.c_void_p()
+        bp = make_params(params)
+        _check(_lib.pp_pm_plan_create(C.byref(bp), self.n_mesh, C.byref(h)), "pp_pm_plan_create")
+        self._h = h
+
+    def accel(self, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        n = pos.shape[1]
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+        _check(_lib.pp_pm_accel(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                _dev(mass, torch.float32, (n,), "mass"), n,
+                                _dev(out, torch.float32, (3, n), "out"), _stream(stream)),
+               "pp_pm_accel")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pp_pm_plan_destroy(h)
+            self._h = None
+
+
+def pp_pm_plan_create(params, n_mesh: int) -> PMPlan:
+    return PMPlan(params, n_mesh)

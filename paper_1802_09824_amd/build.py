@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libphoton_pp.so")
-SOURCES = ["keys_sort.hip", "tree.hip", "pp_kernels.hip", "api.hip"]
+SOURCES = ["keys_sort.hip", "tree.hip", "pp_kernels.hip", "pm.hip", "api.hip"]
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -93,3 +93,23 @@ def test_keys_argument_checks(lib):
     assert lib.pp_hilbert_keys(None, 10, 1.0, 21, None, None) == -1
     assert lib.pp_hilbert_keys(None, 0, 1.0, 0, None, None) == -1
     assert lib.pp_hilbert_keys(None, 0, 1.0, 21, None, None) == 0
+
+
+def test_pm_plan_create_validation(lib):
+    p = Params(L=100.0, rs=3.90625, rcut=17.578125, eps=0.0625, G=1.0, leaf_max=32, key_bits=21)
+    h = C.c_void_p()
+    lib.pp_pm_plan_create.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(C.c_void_p)]
+    for bad in (3, 0, -8, 4096):
+        assert lib.pp_pm_plan_create(C.byref(p), bad, C.byref(h)) == -1
+        assert not h.value
+    q = Params(L=100.0, rs=3.90625, rcut=60.0, eps=0.0625, G=1.0, leaf_max=32, key_bits=21)
+    assert lib.pp_pm_plan_create(C.byref(q), 32, C.byref(h)) == -4
+    rc = lib.pp_pm_plan_create(C.byref(p), 32, C.byref(h))
+    import torch
+    if not torch.cuda.is_available():
+        assert rc == -3            # PP_EDEVICE: no GPU here
+    elif rc == 0:
+        lib.pp_pm_plan_destroy.argtypes = [C.c_void_p]
+        lib.pp_pm_plan_destroy(h)
+    lib.pp_pm_accel.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    assert lib.pp_pm_accel(None, None, None, 0, None, None) == -1
