@@ -271,6 +271,47 @@ int pp_pm_accel(pp_pm_plan* plan, const double* pos, const float* mass, int64_t 
                 void* stream);
 void pp_pm_plan_destroy(pp_pm_plan* plan);
 
+/* ---------------------------------------------------------------------
+ * Adaptive Kick-Drift-Kick integration (sec. 3.4)
+ * ---------------------------------------------------------------------
+ * Drives the whole force, pp_accel + pp_pm_accel (n_mesh = 0: short range
+ * only), for a non-expanding periodic box: kick v += a h, drift x += v h
+ * (wrapped into [0, L)).  Each particle's step is dt / 2^k, with the
+ * smallest k in [0, max_level] meeting dt / 2^k <= sqrt(2 eta eps / |a|)
+ * (the Gadget-2 criterion that sec. 3.4 follows).  Levels are set from the
+ * forces at the start of a top step.  A top step runs 2^K substeps (K the
+ * deepest level in use): opening half kicks where a particle's step starts,
+ * a drift of all particles, the forces (for all particles), closing half
+ * kicks where a step ends.
+ *
+ * pp_kdk_create: p as for pp_plan_create, with eps > 0 (it enters the step
+ *   criterion); n particles; eta > 0; 0 <= max_level <= 15.  The object owns
+ *   a PP plan, a PM plan (n_mesh > 0) and FP32 force buffers.
+ * pp_kdk_init: the forces at the initial positions (needed once).
+ * pp_kdk_step: one top step of length dt > 0 on pos (FP64 [3][n], updated
+ *   in place), vel (FP64 [3][n], updated in place) with masses mass (FP32
+ *   [n]); device pointers; enqueued on the stream.  Synchronises the stream
+ *   once per step to read the level histogram.
+ * pp_kdk_get_info: counters of the object.
+ * pp_kdk_levels: copies the levels of the last step (int8 [n], device).
+ * pp_kdk_accel: copies the current forces (FP32 [3][n] short range, then
+ *   with PM [3][n] long range: 6n floats), device. */
+typedef struct pp_kdk pp_kdk;
+typedef struct pp_kdk_info {
+    int32_t deepest_level, pad;  /* K of the last top step */
+    int64_t top_steps;           /* pp_kdk_step calls */
+    int64_t force_evaluations;   /* including the one of pp_kdk_init */
+    int64_t level_count[16];     /* particles per level in the last top step */
+} pp_kdk_info;
+int pp_kdk_create(const pp_box_params* p, int32_t n_mesh, int64_t n, double eta, int32_t max_level,
+                  pp_kdk** out);
+int pp_kdk_init(pp_kdk* k, const double* pos, const float* mass, void* stream);
+int pp_kdk_step(pp_kdk* k, double* pos, double* vel, const float* mass, double dt, void* stream);
+int pp_kdk_get_info(const pp_kdk* k, pp_kdk_info* out);
+int pp_kdk_levels(const pp_kdk* k, int8_t* level, void* stream);
+int pp_kdk_accel(const pp_kdk* k, float* acc, void* stream);
+void pp_kdk_destroy(pp_kdk* k);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,13 @@ _SIGS = {
     "pp_pm_plan_create": (_i32, [C.POINTER(pp_box_params), _i32, C.POINTER(_P)]),
     "pp_pm_accel": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_pm_plan_destroy": (None, [_P]),
+    "pp_kdk_create": (_i32, [C.POINTER(pp_box_params), _i32, _i64, C.c_double, _i32, C.POINTER(_P)]),
+    "pp_kdk_init": (_i32, [_P, _P, _P, _P]),
+    "pp_kdk_step": (_i32, [_P, _P, _P, _P, C.c_double, _P]),
+    "pp_kdk_get_info": (_i32, [_P, _P]),
+    "pp_kdk_levels": (_i32, [_P, _P, _P]),
+    "pp_kdk_accel": (_i32, [_P, _P, _P]),
+    "pp_kdk_destroy": (None, [_P]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -396,3 +403,55 @@ class PMPlan:
 
 def pp_pm_plan_create(params, n_mesh: int) -> PMPlan:
     return PMPlan(params, n_mesh)
+
+
+class pp_kdk_info(C.Structure):
+    _fields_ = [("deepest_level", C.c_int32), ("pad", C.c_int32), ("top_steps", C.c_int64),
+                ("force_evaluations", C.c_int64), ("level_count", C.c_int64 * 16)]
+
+
+class KDK:
+    """Adaptive KDK integration over pp_accel + pp_pm_accel (pp_kdk_*).
+    pos and vel are FP64 [3][n] device tensors updated in place."""
+
+    def __init__(self, params, n: int, n_mesh: int = 0, eta: float = 0.025, max_level: int = 8):
+        self.n = int(n)
+        self.pm = int(n_mesh) > 0
+        h = C.c_void_p()
+        bp = make_params(params)
+        _check(_lib.pp_kdk_create(C.byref(bp), int(n_mesh), self.n, float(eta), int(max_level), C.byref(h)),
+               "pp_kdk_create")
+        self._h = h
+
+    def init(self, pos: torch.Tensor, mass: torch.Tensor, stream=None):
+        _check(_lib.pp_kdk_init(self._h, _dev(pos, torch.float64, (3, self.n), "pos"),
+                                _dev(mass, torch.float32, (self.n,), "mass"), _stream(stream)), "pp_kdk_init")
+
+    def step(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, stream=None):
+        _check(_lib.pp_kdk_step(self._h, _dev(pos, torch.float64, (3, self.n), "pos"),
+                                _dev(vel, torch.float64, (3, self.n), "vel"),
+                                _dev(mass, torch.float32, (self.n,), "mass"), float(dt), _stream(stream)),
+               "pp_kdk_step")
+
+    def info(self) -> dict:
+        i = pp_kdk_info()
+        _check(_lib.pp_kdk_get_info(self._h, C.byref(i)), "pp_kdk_get_info")
+        return {"deepest_level": i.deepest_level, "top_steps": i.top_steps,
+                "force_evaluations": i.force_evaluations, "level_count": list(i.level_count)}
+
+    def levels(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.int8, device="cuda")
+        _check(_lib.pp_kdk_levels(self._h, C.c_void_p(out.data_ptr()), _stream(stream)), "pp_kdk_levels")
+        return out
+
+    def accel(self, stream=None) -> torch.Tensor:
+        """Current forces: [3][n] short range, and [3][n] long range with PM."""
+        out = torch.empty((6 if self.pm else 3, self.n), dtype=torch.float32, device="cuda")
+        _check(_lib.pp_kdk_accel(self._h, C.c_void_p(out.data_ptr()), _stream(stream)), "pp_kdk_accel")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pp_kdk_destroy(h)
+            self._h = None
