@@ -168,8 +168,20 @@ typedef struct pp_stats {
     int64_t interactions;   /* pairs with s < rcut, j != i (set by pp_count_interactions), else -1 */
     double pp_kernel_ms;    /* duration of the last PP kernel launch (HIP events on the
                                caller's stream) when timing is on, else -1 */
+    int64_t monopoles;      /* (target, monopole) pairs of the last pp_accel with
+                               monopole acceptance on (0 when off, -1 if unknown) */
 } pp_stats;
 /* Waits for the last PP kernel when timing is on.                          */
+/* Monopole acceptance (sec. 3.4, the 1-to-N case of the dual tree walk) for
+ * pp_accel on this plan: a source tree node of 64 leaves or more whose box
+ * satisfies (A + B) / R <= theta against the target block (A, B the longest
+ * box sides, R the distance of the box centres; this implies
+ * B / (R - A) <= theta) acts through its mass at its centre of mass, with
+ * the same softened, split, cut pair force, instead of through its
+ * particles.  theta = 0 (the default) keeps the exact pair sums; 0 <= theta
+ * < 1.  Only the FP32 pp_accel uses it: pp_accel_f64 stays exact, and
+ * pp_count_interactions refuses lists built with monopoles (PP_EINVAL). */
+int pp_plan_set_monopole(pp_plan* plan, double theta);
 int pp_plan_stats(pp_plan* plan, pp_stats* out);
 
 /* Turn HIP-event timing of the PP kernel on (1) or off (0).  With graph

@@ -48,7 +48,8 @@ class pp_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("nleaf", C.c_int64), ("nblock", C.c_int64),
                 ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
                 ("evaluated", C.c_int64), ("lane_pairs", C.c_int64),
-                ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double)]
+                ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double),
+                ("monopoles", C.c_int64)]
 
 
 _P, _i64, _i32, _dbl, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_size_t
@@ -71,6 +72,7 @@ _SIGS = {
     "pp_accel": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_accel_f64": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
+    "pp_plan_set_monopole": (_i32, [_P, C.c_double]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
     "pp_plan_set_timing": (_i32, [_P, _i32]),
     "pp_plan_get_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
@@ -263,6 +265,10 @@ class Plan:
 
     def set_timing(self, on: bool = True):
         _check(_lib.pp_plan_set_timing(self._h, 1 if on else 0), "pp_plan_set_timing")
+
+    def set_monopole(self, theta: float):
+        """Monopole acceptance for accel (0 = exact pair sums)."""
+        _check(_lib.pp_plan_set_monopole(self._h, float(theta)), "pp_plan_set_monopole")
 
     def get_tuning(self) -> dict:
         t = pp_tuning()

@@ -114,6 +114,8 @@ struct Batch {
     pp_tuning tune{2048, 1, 20, 0, 0, 1};
     int64_t graph_variant = -1;
     bool table_ready = false;      // the interpolated split table is built
+    double theta = 0.0;            // monopole acceptance (0: exact pair sums)
+    bool lists_mono = false;       // the current lists hold monopoles
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
     bool timing = false, timed = false;
@@ -200,7 +202,12 @@ struct Batch {
                             w.bad.as<int>(), &bad));
         if (bad) return fail(PP_EINVAL, "non-finite position or mass");
         PP_TRY(stage_trees(bd, w, s));
-        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s));
+        // monopoles only on the FP32 path: the FP64 yardstick and the pair
+        // count keep exact lists
+        const bool mono = mass_f != nullptr && theta > 0.0;
+        if (mono) PP_TRY(stage_node_moments(bd, w, s));
+        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mono ? theta * theta : 0.0));
+        lists_mono = mono;
         st.n = N;
         st.nleaf = w.nleaf;
         st.nblock = w.nblock;
@@ -217,7 +224,7 @@ struct Batch {
 
     int run_pp_direct(float* acc, hipStream_t s) {
         unsigned long long* ctr = counters.as<unsigned long long>();
-        PP_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), s));
+        PP_HIP(hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s));
         if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
         if (timing) PP_HIP(hipEventRecord(ev0, s));
         PP_TRY(launch_pp_f32(bd, w, tune.groups, tune.persistent ? Mode::kPersistent : Mode::kGrid,
@@ -228,6 +235,7 @@ struct Batch {
             timed = true;
         }
         PP_TRY(launch_reduce_f32(bd, w, partial.as<float>(), acc, s));
+        if (lists_mono) PP_TRY(launch_monopole(bd, w, acc, ctr + 2, s));
         evaluated_valid = true;
         return PP_OK;
     }
@@ -278,6 +286,7 @@ struct Batch {
                 PP_HIP(hipEventRecord(ev1, s));
                 timed = true;
             }
+            if (lists_mono) PP_TRY(launch_monopole(bd, w, acc, nullptr, s));
             evaluated_valid = false;
             return PP_OK;
         }
@@ -293,11 +302,13 @@ struct Batch {
             st.pp_kernel_ms = ms;
         }
         st.evaluated = st.lane_pairs = -1;
+        st.monopoles = lists_mono ? -1 : 0;
         if (evaluated_valid) {
-            unsigned long long h[2] = {0, 0};
+            unsigned long long h[3] = {0, 0, 0};
             PP_HIP(hipMemcpy(h, counters.p, sizeof(h), hipMemcpyDeviceToHost));
             st.evaluated = (int64_t)h[0];
             st.lane_pairs = (int64_t)h[1];
+            if (lists_mono) st.monopoles = (int64_t)h[2];
         }
         *out = st;
         return PP_OK;
@@ -709,6 +720,14 @@ int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, 
     return PP_OK;
 }
 
+int pp_plan_set_monopole(pp_plan* pl, double theta) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    if (!(theta >= 0.0 && theta < 1.0)) return fail(PP_EINVAL, "theta must be in [0, 1)");
+    pl->b.theta = theta;
+    pl->b.lists_valid = false;
+    return PP_OK;
+}
+
 int pp_plan_stats(pp_plan* pl, pp_stats* out) {
     if (!pl || !out) return fail(PP_EINVAL, "NULL argument");
     return pl->b.stats(out);
@@ -735,6 +754,8 @@ int pp_plan_set_tuning(pp_plan* pl, const pp_tuning* t) {
 
 static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStream_t s) {
     if (!b.lists_valid) return fail(PP_EINVAL, "no lists: call the accel function first");
+    if (b.lists_mono)
+        return fail(PP_EINVAL, "the lists hold monopoles: count after pp_accel_f64 or with theta 0");
     PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.nitem + 1)));
     PP_TRY(launch_count(b.bd, b.w, b.w.chunk, b.pcount.as<int32_t>(), s));
     unsigned long long* tot = b.w.misc.as<unsigned long long>() + 4;

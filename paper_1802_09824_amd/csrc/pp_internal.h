@@ -131,12 +131,26 @@ struct BatchDev {
 };
 
 // ------------------------------------------------------------- workspace --
+// One entry of the near-list expansion: (target block, periodic image,
+// source tree node at a level).
+struct FEntry {
+    int32_t blk;
+    int32_t node;
+    uint8_t sc;      // shift code
+    uint8_t lev;     // tree level of node
+    uint8_t inside;  // whole subtree within r_cut
+    uint8_t mono;    // taken as a monopole (monopole acceptance on)
+};
+
 struct Work {
     int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
     DevBuf mass_flag;        // int32 [nbox]: 1 where the box's FP32 masses are not all equal
     DevBuf split_tab;        // float4 [128]: the interpolated split table (variant bit 8)
+    DevBuf tree_mc;          // double4 per tree node: sum m x, sum m y, sum m z, sum m
+    const FEntry* ent_final = nullptr;   // the list expansion's final entries (nentry)
+    std::vector<int64_t> lvl_prefix_host;
     DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
     DevBuf lam, pmax, smax, level_p, flag, flag_off;
@@ -188,8 +202,15 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
                  Work& w, hipStream_t s, const int* bad_dev = nullptr, int* bad_host = nullptr);
 int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);
+// theta2 > 0: monopole acceptance with theta^2 = theta2 (nodes of level >= 2)
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s);
+                hipStream_t s, double theta2 = 0.0);
+// Mass and mass-weighted position sums of every tree node (after stage_trees;
+// needs the FP32 masses in key order).
+int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s);
+// Adds the monopoles' forces to acc (input order), FP32 path.
+int launch_monopole(const BatchDev& bd, const Work& w, float* acc, unsigned long long* counter,
+                    hipStream_t s);
 int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t T, DevBuf& row_cnt,
                           DevBuf& row_ptr, DevBuf& src, DevBuf& code, DevBuf& scan_ws,
                           int64_t* nentries, hipStream_t s);

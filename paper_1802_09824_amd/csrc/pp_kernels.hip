@@ -377,6 +377,87 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     o[2 * kBlock + lane] = (float)(((double)az - (double)cz) * (double)mu);
 }
 
+// Monopoles (sec. 3.4, 1 to N): one wave per target block walks the block's
+// entries of the list expansion; accepted nodes become sources of their
+// mass at their centre of mass (FP64 sums, shifted by their periodic
+// image, relative to the FP64 block centre, in units of ell) and go through
+// the same pair arithmetic as particles, with the same cut.  The result is
+// added to the accelerations the PP path wrote.
+__global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry* __restrict__ ent,
+                                                      const int64_t* __restrict__ eoff,
+                                                      const TreeView* __restrict__ tvs,
+                                                      const double4* __restrict__ mc,
+                                                      const double* __restrict__ pos_s, int64_t N,
+                                                      int64_t nblock,
+                                                      unsigned long long* __restrict__ counter) {
+    __shared__ float4 tile[kBlock];
+    const int64_t b = blockIdx.x;
+    if (b >= nblock) return;
+    const int lane = threadIdx.x;
+    const int xbox = ia.bboxid[b];
+    const BoxDev& X = ia.box[xbox];
+    const TreeView& tv = tvs[xbox];
+    const double L = X.L, cell = X.cell, inv_len = X.inv_len;
+    const PolyF32 P = X.poly;
+    const IBox B = ia.bbox[b];
+    const double ox = 0.5 * (double)(B.lo[0] + B.hi[0]) * cell;
+    const double oy = 0.5 * (double)(B.lo[1] + B.hi[1]) * cell;
+    const double oz = 0.5 * (double)(B.lo[2] + B.hi[2]) * cell;
+    const int32_t nt = ia.bcount[b];
+    const int64_t t = (int64_t)ia.bstart[b] + lane;
+    float xi = 0.f, yi = 0.f, zi = 0.f;
+    if (lane < nt) {
+        xi = (float)((pos_s[t] - ox) * inv_len);
+        yi = (float)((pos_s[N + t] - oy) * inv_len);
+        zi = (float)((pos_s[2 * N + t] - oz) * inv_len);
+    }
+    float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    int64_t taken = 0;
+    const int64_t e_end = eoff[b + 1];
+    for (int64_t e0 = eoff[b]; e0 < e_end; e0 += kBlock) {
+        const int64_t e = e0 + lane;
+        bool keep = false;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < e_end) {
+            const FEntry E = ent[e];
+            if (E.mono) {
+                const double4 m = mc[tv.off[E.lev] + E.node];
+                if (m.w > 0.0) {
+                    keep = true;
+                    const double sx = (double)(E.sc / 9 - 1) * L;
+                    const double sy = (double)((E.sc / 3) % 3 - 1) * L;
+                    const double sz = (double)(E.sc % 3 - 1) * L;
+                    v.x = (float)((m.x / m.w + sx - ox) * inv_len);
+                    v.y = (float)((m.y / m.w + sy - oy) * inv_len);
+                    v.z = (float)((m.z / m.w + sz - oz) * inv_len);
+                    v.w = (float)m.w;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(keep);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (keep) tile[rank] = v;
+        const int cnt = __popcll(bal);
+        taken += cnt;
+        wave_sync();
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        for (int q = 0; q < cnt; ++q) pair_f32<false>(tile[q], xi, yi, zi, P, tx, ty, tz);
+        kahan_add(ax, cx, tx);
+        kahan_add(ay, cy, ty);
+        kahan_add(az, cz, tz);
+        wave_sync();
+    }
+    if (taken == 0) return;
+    if (lane < nt) {
+        const int64_t i = ia.perm[t];
+        ia.acc[i] += (float)(((double)ax - (double)cx) * X.scale);
+        ia.acc[N + i] += (float)(((double)ay - (double)cy) * X.scale);
+        ia.acc[2 * N + i] += (float)(((double)az - (double)cz) * X.scale);
+    }
+    if (counter && lane == 0) atomicAdd(counter, (unsigned long long)taken * (unsigned long long)nt);
+}
+
 // One workgroup per item.
 // Both forms are bounded to 80 VGPRs (6 waves per SIMD): two waves' VALU
 // instructions can issue in the same cycle, so more resident waves keep the
@@ -720,6 +801,18 @@ int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int 
         case 14: return launch_pp_f32_var<14>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         default: return launch_pp_f32_var<15>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
     }
+}
+
+int launch_monopole(const BatchDev& bd, const Work& w, float* acc, unsigned long long* counter,
+                    hipStream_t s) {
+    if (w.nblock == 0 || !w.ent_final) return PP_OK;
+    ItemArgs ia = item_args(bd, w, 0);
+    ia.acc = acc;
+    hipLaunchKernelGGL(monopole_kernel, dim3((unsigned)w.nblock), dim3(kBlock), 0, s, ia, w.ent_final,
+                       w.eoff.as<int64_t>(), w.tviews.as<TreeView>(), w.tree_mc.as<double4>(),
+                       w.pos_s.as<double>(), w.pos_n, w.nblock, counter);
+    PP_HIP(hipGetLastError());
+    return PP_OK;
 }
 
 int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,

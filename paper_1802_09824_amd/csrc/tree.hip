@@ -183,6 +183,47 @@ __global__ void tree_level_kernel(const TreeView* __restrict__ tv, const int64_t
     nodes[T.off[h] + i] = P;
 }
 
+// Mass and mass-weighted position sums of every tree node (x, y, z: sum of
+// m x; w: sum of m), FP64, for monopole acceptance.  Level 0 from the
+// particles of each leaf, in order; level h from its (up to 8) children.
+__global__ void leaf_moment_kernel(const double* __restrict__ pos_s, const float* __restrict__ mass_s,
+                                   int64_t N, const int64_t* __restrict__ begin, int64_t m,
+                                   double4* __restrict__ mc) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    const int64_t b0 = begin[a], b1 = a + 1 < m ? begin[a + 1] : N;
+    double sx = 0, sy = 0, sz = 0, sm = 0;
+    for (int64_t k = b0; k < b1; ++k) {
+        const double mk = (double)mass_s[k];
+        sx += mk * pos_s[k];
+        sy += mk * pos_s[N + k];
+        sz += mk * pos_s[2 * N + k];
+        sm += mk;
+    }
+    mc[a] = make_double4(sx, sy, sz, sm);
+}
+
+__global__ void tree_moment_kernel(const TreeView* __restrict__ tv, const int64_t* __restrict__ lp,
+                                   int nbox, int h, double4* __restrict__ mc) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= lp[nbox]) return;
+    const int x = box_of(lp, nbox, g);
+    const TreeView& T = tv[x];
+    const int64_t i = g - lp[x];
+    const int64_t nchild = T.cnt[h - 1];
+    const double4* child = mc + T.off[h - 1];
+    double4 P = child[8 * i];
+    const int64_t e = 8 * i + 8 < nchild ? 8 * i + 8 : nchild;
+    for (int64_t c = 8 * i + 1; c < e; ++c) {
+        const double4 C = child[c];
+        P.x += C.x;
+        P.y += C.y;
+        P.z += C.z;
+        P.w += C.w;
+    }
+    mc[T.off[h] + i] = P;
+}
+
 // ------------------------------------------------------------ box tests --
 // Gap along one axis between target [loA, hiA) and source [loB, hiB)
 // shifted by s * W (grid units).
@@ -252,6 +293,28 @@ __device__ __forceinline__ int64_t gap2_min(const IBox& A, const IBox& B, const 
         r += best * best;
     }
     return r;
+}
+
+// Monopole acceptance of node box B for target box A under shift s
+// (sec. 3.4): (A + B) / R <= theta with A, B the longest box sides and R
+// the distance of the box centres, tested as (2 (A + B))^2 <= theta^2
+// (2R)^2 with 2R from integer half-cell coordinates.  Every operation is
+// exact except the two products on the right, so the decision does not
+// depend on the evaluation order of the caller.  (For theta < 1 it also
+// gives B / (R - A) <= theta.)
+__device__ __forceinline__ bool accept_monopole(const IBox& A, const IBox& B, const int s[3], int64_t W,
+                                                double theta2) {
+#pragma clang fp contract(off)
+    int64_t a = 0, b = 0, r2 = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int64_t sa = (int64_t)A.hi[ax] - A.lo[ax], sb = (int64_t)B.hi[ax] - B.lo[ax];
+        a = sa > a ? sa : a;
+        b = sb > b ? sb : b;
+        const int64_t d = ((int64_t)B.lo[ax] + B.hi[ax] + 2 * (int64_t)s[ax] * W) - ((int64_t)A.lo[ax] + A.hi[ax]);
+        r2 += d * d;
+    }
+    const double lhs = (double)(2 * (a + b));
+    return lhs * lhs <= theta2 * (double)r2;
 }
 
 // ------------------------------------------------------- canonical list --
@@ -446,15 +509,10 @@ __global__ void __launch_bounds__(64) block_split_kernel(
 // 8-child test per entry.  Leaves (or inside intervals) come in ascending order and
 // consecutive ones merge into one range of source particles.
 constexpr int kDfsLevel = 2;
+// Monopoles are taken for nodes of this level and up (groups of 64 leaves
+// and more), which the breadth-first expansion always reaches.
+constexpr int kMonoMinLevel = 2;
 
-struct FEntry {
-    int32_t blk;
-    int32_t node;
-    uint8_t sc;      // shift code
-    uint8_t lev;     // tree level of node
-    uint8_t inside;  // whole subtree within r_cut
-    uint8_t pad;
-};
 
 // Test the children of (h, i): pass bits and inside bits (inside implies pass).
 __device__ __forceinline__ void expand2(const TreeView& tv, const IBox* nodes, int h, int64_t i,
@@ -481,7 +539,7 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                 const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                 const int32_t* __restrict__ bboxid, int64_t nb,
                                 int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                FEntry* __restrict__ out) {
+                                FEntry* __restrict__ out, double theta2) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int x = bboxid[b];
@@ -506,7 +564,7 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
             e.sc = (uint8_t)sc;
             e.lev = (uint8_t)top;
             e.inside = maxd2_shift(A, R, s, W) < T;
-            e.pad = 0;
+            e.mono = theta2 > 0.0 && top >= kMonoMinLevel && accept_monopole(A, R, s, W, theta2);
             out[o++] = e;
         } else {
             ++c;
@@ -522,11 +580,14 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                  const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                  const int32_t* __restrict__ bboxid, const FEntry* __restrict__ in,
                                  int64_t F, int stop, int32_t* __restrict__ cnt,
-                                 const int64_t* __restrict__ off, FEntry* __restrict__ out) {
+                                 const int64_t* __restrict__ off, FEntry* __restrict__ out,
+                                 double theta2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= F) return;
     const FEntry E = in[e];
-    if (E.inside || E.lev <= stop) {
+    // with monopole acceptance, inside entries are opened too (a child may
+    // be accepted); accepted entries are final
+    if (E.mono || E.lev <= stop || (E.inside && theta2 == 0.0)) {
         if (FILL) out[off[e]] = E;
         else cnt[e] = 1;
         return;
@@ -550,7 +611,8 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
         C.sc = E.sc;
         C.lev = (uint8_t)(E.lev - 1);
         C.inside = (inside >> c) & 1u;
-        C.pad = 0;
+        C.mono = theta2 > 0.0 && C.lev >= kMonoMinLevel &&
+                 accept_monopole(bbox[E.blk], nodes[tvs[x].off[C.lev] + C.node], s, bd.box[x].W, theta2);
         out[o++] = C;
     }
 }
@@ -598,7 +660,9 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
     const int64_t first = (int64_t)E.node << (3 * E.lev);
     int64_t last = (((int64_t)E.node + 1) << (3 * E.lev)) - 1;
     if (last > nleaf - 1) last = nleaf - 1;
-    if (E.inside || E.lev == 0) {
+    if (E.mono) {
+        // a monopole: no source ranges
+    } else if (E.inside || E.lev == 0) {
         emit(first, last);
     } else {
         uint64_t mask = 0;
@@ -816,6 +880,7 @@ int stage_trees(const BatchDev& bd, Work& w, hipStream_t s) {
     PP_HIP(hipMemcpyAsync(w.tviews.p, w.tv.data(), sizeof(TreeView) * nbox, hipMemcpyHostToDevice, s));
     PP_HIP(hipMemcpyAsync(w.lvl_prefix.p, lp.data(), sizeof(int64_t) * lp.size(),
                           hipMemcpyHostToDevice, s));
+    w.lvl_prefix_host = lp;
     IBox* nodes = w.tree_boxes.as<IBox>();
     if (w.nleaf > 0)
         PP_HIP(hipMemcpyAsync(nodes, w.lboxes.p, sizeof(IBox) * w.nleaf, hipMemcpyDeviceToDevice, s));
@@ -828,6 +893,27 @@ int stage_trees(const BatchDev& bd, Work& w, hipStream_t s) {
     PP_HIP(hipGetLastError());
     // the host vectors above must outlive the asynchronous copies
     PP_HIP(hipStreamSynchronize(s));
+    return PP_OK;
+}
+
+int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s) {
+    const int nbox = bd.nbox;
+    int64_t total = 0;
+    for (int x = 0; x < nbox; ++x)
+        for (int h = 0; h < w.tv[x].nlev; ++h) total += w.tv[x].cnt[h];
+    PP_TRY(w.tree_mc.reserve(sizeof(double4) * (total > 0 ? total : 1)));
+    if (w.nleaf == 0) return PP_OK;
+    const int64_t N = w.pos_n;
+    double4* mc = w.tree_mc.as<double4>();
+    hipLaunchKernelGGL(leaf_moment_kernel, dim3(blocks_for(w.nleaf, 128)), dim3(128), 0, s,
+                       w.pos_s.as<double>(), w.mass_s.as<float>(), N, w.lbegin.as<int64_t>(), w.nleaf, mc);
+    for (int h = 1; h < w.max_levels; ++h) {
+        const int64_t nh = w.lvl_prefix_host[(size_t)h * (nbox + 1) + nbox];
+        hipLaunchKernelGGL(tree_moment_kernel, dim3(blocks_for(nh, 256)), dim3(256), 0, s,
+                           w.tviews.as<TreeView>(), w.lvl_prefix.as<int64_t>() + (size_t)h * (nbox + 1),
+                           nbox, h, mc);
+    }
+    PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
@@ -864,7 +950,7 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
 }
 
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s) {
+                hipStream_t s, double theta2) {
     const int nbox = bd.nbox;
     const int64_t N = poff[nbox];
     w.nblock = w.nentry = w.nrange = w.nitem = w.candidates = 0;
@@ -915,14 +1001,14 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.foff.reserve(sizeof(int64_t) * (nb + 2)));
     hipLaunchKernelGGL(bfs_root_kernel<false>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, nb, w.fcnt.as<int32_t>(), (const int64_t*)nullptr,
-                       (FEntry*)nullptr);
+                       (FEntry*)nullptr, theta2);
     PP_HIP(hipGetLastError());
     PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), nb, w.scan_ws, s));
     PP_TRY(read_back(w.foff.as<int64_t>() + nb, &F, s));
     PP_TRY(cur->reserve(sizeof(FEntry) * (F + 1)));
     hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, nb, (int32_t*)nullptr, w.foff.as<int64_t>(),
-                       cur->as<FEntry>());
+                       cur->as<FEntry>(), theta2);
     PP_HIP(hipGetLastError());
     // Levels above kDfsLevel must be expanded (the masks cover 64 leaves);
     // level 2 -> 1 is taken too when the expanded entries fit the budget.
@@ -933,7 +1019,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         PP_TRY(w.foff.reserve(sizeof(int64_t) * (F + 2)));
         hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd,
                            tvs, nodes, bbox, bboxid, cur->as<FEntry>(), F, stop,
-                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr);
+                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr, theta2);
         PP_HIP(hipGetLastError());
         PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), F, w.scan_ws, s));
         int64_t F2 = 0;
@@ -942,7 +1028,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         PP_TRY(nxt->reserve(sizeof(FEntry) * (F2 + 1)));
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                            nodes, bbox, bboxid, cur->as<FEntry>(), F, stop, (int32_t*)nullptr,
-                           w.foff.as<int64_t>(), nxt->as<FEntry>());
+                           w.foff.as<int64_t>(), nxt->as<FEntry>(), theta2);
         PP_HIP(hipGetLastError());
         DevBuf* t = cur;
         cur = nxt;
@@ -951,6 +1037,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     }
     w.nentry = F;
     const FEntry* ent = cur->as<FEntry>();
+    w.ent_final = ent;
     PP_TRY(w.lmask_e.reserve(sizeof(uint64_t) * (F + 1)));
     PP_TRY(w.rcnt_e.reserve(sizeof(int32_t) * (F + 1)));
     PP_TRY(w.scnt_e.reserve(sizeof(int32_t) * (F + 1)));

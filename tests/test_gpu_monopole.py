@@ -1,0 +1,89 @@
+"""GPU tests of monopole acceptance (pp_plan_set_monopole) against the FP64
+tree oracle (oracle/tree.py), which walks the same target blocks and
+source nodes.  The acceptance decisions are exact integer/FP64 tests on
+both sides, so the number of (target, monopole) pairs must agree exactly;
+the accelerations agree to FP32 rounding."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import BoxParams
+from tests import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_09824_amd as m
+    return m
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.fixture(scope="module")
+def box():
+    rng = np.random.default_rng(3)
+    n, L = 16000, 60.0
+    pos = W.mixture(rng, n, L, 0.7, 6)
+    b = BoxParams.from_mesh(L, 32)
+    p = BoxParams(L=b.L, rs=b.rs, rcut=b.rcut, eps=b.eps, leaf_max=4)
+    mass = rng.uniform(0.5, 1.5, n).astype(np.float32) / n
+    return pos, mass, p
+
+
+def rel(acc, ref):
+    mag = np.linalg.norm(ref, axis=0)
+    return np.linalg.norm(acc.astype(np.float64) - ref, axis=0) / np.maximum(mag, 1e-300)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5])
+def test_monopoles_match_tree_oracle(pp, box, theta):
+    from oracle import tree
+    pos, mass, p = box
+    ref = tree.monopole_accel(pos, mass.astype(np.float64), p, theta)
+    plan = pp.Plan(p, pos.shape[1])
+    plan.set_monopole(theta)
+    acc = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    st = plan.stats()
+    assert st["monopoles"] == ref["n_mono_pairs"] > 0, (st["monopoles"], ref["n_mono_pairs"])
+    e = rel(acc, ref["acc"])
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99.9) <= 1e-4, (np.median(e), np.percentile(e, 99.9))
+
+
+def test_theta_zero_and_tiny_are_exact(pp, box, oracle_mod):
+    pos, mass, p = box
+    ref = oracle_mod.accel(pos, mass.astype(np.float64), p)
+    plan = pp.Plan(p, pos.shape[1])
+    a0 = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    assert plan.stats()["monopoles"] == 0
+    plan.set_monopole(1e-9)
+    a1 = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    assert plan.stats()["monopoles"] == 0
+    for a in (a0, a1):
+        s = parity.summary(a, ref)
+        assert s["zero_ok"] and s["median"] <= 1e-6 and s["p999"] <= 1e-4, s
+    plan.set_monopole(0.0)
+    a2 = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    assert np.array_equal(a2, a0)
+
+
+def test_monopole_mode_keeps_f64_exact_and_refuses_counts(pp, box, oracle_mod):
+    pos, mass, p = box
+    plan = pp.Plan(p, pos.shape[1])
+    plan.set_monopole(0.5)
+    plan.accel(dev(pos, torch.float64), dev(mass, torch.float32))
+    with pytest.raises(pp.PPError):
+        plan.count_interactions()
+    ref = oracle_mod.accel(pos, mass.astype(np.float64), p)
+    a64 = plan.accel_f64(dev(pos, torch.float64), dev(mass.astype(np.float64), torch.float64)).cpu().numpy()
+    assert parity.summary(a64, ref)["max"] <= 1e-10
+    tot = plan.count_interactions()               # the FP64 call left exact lists
+    assert tot == int(ref["n_inter"].sum())
+    with pytest.raises(pp.PPError):
+        plan.set_monopole(1.0)
