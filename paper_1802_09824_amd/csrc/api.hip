@@ -1,7 +1,8 @@
 // C ABI of the library (include/photon_pp.h): argument checks, plans, the
 // order of the path's stages, the batched persistent launch and its graph,
 // and the autotuner.  All compute runs in the HIP kernels of keys_sort.hip,
-// tree.hip and pp_kernels.hip.
+// tree.hip and pp_kernels.hip (the PM force and the KDK driver have their
+// own entry points in pm.hip and kdk.hip).
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -113,26 +113,41 @@ __global__ void __launch_bounds__(256) keys_raw_kernel(const double* __restrict_
     keys[k] = key_of(pos[k], pos[n + k], pos[2 * n + k], L, scale, b);
 }
 
+// Input order -> one 32-byte record per particle (wrapped position, mass),
+// read and written in order, so that the permuted gather below touches one
+// record per particle instead of four arrays.
 template <class M>
-__global__ void __launch_bounds__(256) gather_kernel(BatchDev bd, const double* __restrict__ pos,
-                                                     const M* __restrict__ mass,
-                                                     const int32_t* __restrict__ perm, int64_t N,
-                                                     double* __restrict__ pos_s,
-                                                     M* __restrict__ mass_s, int* bad) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    const double L = bd.box[box_of(bd.poff, bd.nbox, k)].L;
-    const int64_t i = perm[k];
-    for (int a = 0; a < 3; ++a) {
-        const double x = pos[a * N + i];
-        pos_s[a * N + k] = isfinite(x) ? wrap_pos(x, L) : 0.0;
-    }
+__global__ void __launch_bounds__(256) pack_kernel(BatchDev bd, const double* __restrict__ pos,
+                                                   const M* __restrict__ mass, int64_t N,
+                                                   double4* __restrict__ rec, int* bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double L = bd.box[box_of(bd.poff, bd.nbox, i)].L;
+    double4 r;
+    const double x = pos[i], y = pos[N + i], z = pos[2 * N + i];
+    r.x = isfinite(x) ? wrap_pos(x, L) : 0.0;
+    r.y = isfinite(y) ? wrap_pos(y, L) : 0.0;
+    r.z = isfinite(z) ? wrap_pos(z, L) : 0.0;
     M m = mass[i];
     if (!isfinite((double)m)) {
         atomicOr(bad, 1);
         m = 0;
     }
-    mass_s[k] = m;
+    r.w = (double)m;
+    rec[i] = r;
+}
+
+template <class M>
+__global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__ rec,
+                                                     const int32_t* __restrict__ perm, int64_t N,
+                                                     double* __restrict__ pos_s, M* __restrict__ mass_s) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double4 r = rec[perm[k]];
+    pos_s[k] = r.x;
+    pos_s[N + k] = r.y;
+    pos_s[2 * N + k] = r.z;
+    mass_s[k] = (M)r.w;
 }
 
 __global__ void set_zero_i64(int64_t* p) { *p = 0; }
@@ -291,14 +306,20 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
 int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* mass_f,
                  const double* mass_d, Work& w, hipStream_t s) {
     if (N == 0) return PP_OK;
-    if (mass_f)
-        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos,
-                           mass_f, w.perm.as<int32_t>(), N, w.pos_s.as<double>(),
-                           w.mass_s.as<float>(), w.bad.as<int>());
-    else
-        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd,
-                           pos, mass_d, w.perm.as<int32_t>(), N, w.pos_s.as<double>(),
-                           w.mass_sd.as<double>(), w.bad.as<int>());
+    PP_TRY(w.rec.reserve(sizeof(double4) * N));
+    double4* rec = w.rec.as<double4>();
+    const int32_t* perm = w.perm.as<int32_t>();
+    if (mass_f) {
+        hipLaunchKernelGGL(pack_kernel<float>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos, mass_f, N,
+                           rec, w.bad.as<int>());
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks_for(N, 256)), dim3(256), 0, s, rec, perm, N,
+                           w.pos_s.as<double>(), w.mass_s.as<float>());
+    } else {
+        hipLaunchKernelGGL(pack_kernel<double>, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos, mass_d,
+                           N, rec, w.bad.as<int>());
+        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks_for(N, 256)), dim3(256), 0, s, rec, perm, N,
+                           w.pos_s.as<double>(), w.mass_sd.as<double>());
+    }
     PP_HIP(hipGetLastError());
     return PP_OK;
 }

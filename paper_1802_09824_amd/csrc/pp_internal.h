@@ -146,6 +146,7 @@ struct Work {
     int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
+    DevBuf rec;              // double4 [N]: wrapped position and mass, input order (gather staging)
     DevBuf mass_flag;        // int32 [nbox]: 1 where the box's FP32 masses are not all equal
     DevBuf split_tab;        // float4 [128]: the interpolated split table (variant bit 8)
     DevBuf tree_mc;          // double4 per tree node: sum m x, sum m y, sum m z, sum m

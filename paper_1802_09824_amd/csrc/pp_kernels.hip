@@ -208,7 +208,7 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 // 64 ranges from the wave's range cursor) and loads the FP64 position and
 // the mass; the loads of the next window are issued before the current tile
 // is swept.  A fetched source is shifted by its periodic image, made
-// relative to the FP64 block centre, scaled by 1/r_cut and rounded to FP32,
+// relative to the FP64 block centre, scaled by 1/ell and rounded to FP32,
 // and dropped if it lies at r_cut or more from the block's box.  Survivors
 // are compacted with a ballot into a 128-entry LDS ring; every 64 survivors
 // are swept by all lanes with broadcast LDS reads.
@@ -520,7 +520,7 @@ __global__ void reset_queues_kernel(unsigned* q) {
 }
 
 // One thread per (block, lane), grid-stride: sum the item partials of the
-// block in order (FP64), scale by G / r_cut^2, scatter to input order.
+// block in order (FP64), scale by G / ell^2, scatter to input order.
 __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
                                                          const float* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
