@@ -182,6 +182,21 @@ typedef struct pp_stats {
  * < 1.  Only the FP32 pp_accel uses it: pp_accel_f64 stays exact, and
  * pp_count_interactions refuses lists built with monopoles (PP_EINVAL). */
 int pp_plan_set_monopole(pp_plan* plan, double theta);
+/* Gadget-2's relative opening criterion (sec. 3.1) for the same monopole
+ * acceptance: a node of mass M is taken only if G M B^2 / r^4 <= alpha |a|,
+ * with B its longest box side, r the gap between its box and the target
+ * block's box (0 for touching boxes, which are therefore always opened) and
+ * |a| the smallest reference acceleration among the block's targets.
+ * acc_ref: device FP32 [3][n] (x row, y row, z row) in input order, for
+ * instance the accelerations of the previous step; it is copied on `stream`
+ * (the caller may free it once the stream reaches this point) and must
+ * describe the n particles of the following pp_accel calls (PP_EINVAL
+ * otherwise).  When theta > 0 as well, a node must pass both tests.
+ * alpha = 0 turns the test off (acc_ref may then be NULL).  Errors:
+ * PP_EINVAL for alpha < 0 or non-finite, NULL acc_ref with alpha > 0, n
+ * outside 1..the plan's capacity. */
+int pp_plan_set_monopole_relative(pp_plan* plan, double alpha, const float* acc_ref, int64_t n,
+                                  void* stream);
 int pp_plan_stats(pp_plan* plan, pp_stats* out);
 
 /* Turn HIP-event timing of the PP kernel on (1) or off (0).  With graph

@@ -18,11 +18,14 @@ the algorithm's order:
   its mass and its centre of mass;
 * per target node A and periodic image s, walk the source tree from the
   root: a node whose box lies at r_cut or more from A's box is skipped; a
-  node of level >= 2 is taken as a monopole when (A + B) / R <= theta
-  (A, B the longest box sides, R the distance of the box centres; for
-  theta < 1 this also gives B / (R - A) <= theta); other nodes are opened;
-  leaves reached this way are summed particle by particle (the N-to-M PP of
-  sec. 3.3);
+  node of level >= 2 is taken as a monopole when every enabled test holds:
+  the geometric one, (A + B) / R <= theta (A, B the longest box sides, R
+  the distance of the box centres; for theta < 1 this also gives
+  B / (R - A) <= theta), and Gadget-2's relative one of sec. 3.1,
+  G M B^2 / r^4 <= alpha |a| (M the node mass, r the gap between the two
+  boxes, |a| the smallest reference acceleration among A's targets); other
+  nodes are opened; leaves reached this way are summed particle by particle
+  (the N-to-M PP of sec. 3.3);
 * a monopole acts on every target of A as a particle of the node's mass at
   its centre of mass: the same softened, split, cut pair force.
 """
@@ -68,18 +71,40 @@ def _gap2(alo, ahi, blo, bhi, s, W):
     return int((g * g).sum())
 
 
-def _accept(alo, ahi, blo, bhi, s, W, theta):
+def _accept(alo, ahi, blo, bhi, s, W, theta, rel=None):
+    """The enabled acceptance tests, each squared so that it is a fixed
+    sequence of FP64 operations on integers and the given masses: the
+    geometric one as (2 (A + B))^2 <= theta^2 (2 R)^2 in half cells, the
+    relative one as (G M (B cell)^2)^2 <= alpha^2 |a|^2 (r cell)^8.
+    rel = (G, M, cell, alpha, |a|^2) or None."""
     A = int((ahi - alo).max())
     B = int((bhi - blo).max())
-    D = (blo + bhi + 2 * np.asarray(s, dtype=np.int64) * W) - (alo + ahi)
-    R2x4 = int((D * D).sum())
-    lhs = float(2 * (A + B)) ** 2
-    return lhs <= (theta * theta) * float(R2x4)
+    if theta > 0:
+        D = (blo + bhi + 2 * np.asarray(s, dtype=np.int64) * W) - (alo + ahi)
+        R2x4 = int((D * D).sum())
+        lhs = float(2 * (A + B)) ** 2
+        if not lhs <= (theta * theta) * float(R2x4):
+            return False
+    if rel is not None:
+        G, M, cell, alpha, a2 = rel
+        bc = float(B) * cell
+        lhs = ((G * M) * bc) * bc
+        g2 = (float(_gap2(alo, ahi, blo, bhi, s, W)) * cell) * cell
+        if not lhs * lhs <= ((alpha * alpha) * a2) * ((g2 * g2) * (g2 * g2)):
+            return False
+    return True
 
 
-def monopole_accel(pos, mass, params, theta, min_level=2):
+def _seq_sum(v):
+    """Sum in index order (the order of the node moments' definition)."""
+    return np.cumsum(v, axis=0)[-1]
+
+
+def monopole_accel(pos, mass, params, theta, min_level=2, alpha=0.0, acc_ref=None):
     """Accelerations [3][n] (input order) with monopole acceptance, and the
-    number of (target, monopole) and (target, source particle) pairs taken."""
+    number of (target, monopole) and (target, source particle) pairs taken.
+    theta: the geometric test (0: off); alpha > 0 adds the relative test
+    against acc_ref [3][n] (input order)."""
     p = params
     pos = np.asarray(pos, dtype=np.float64)
     mass = np.asarray(mass, dtype=np.float64)
@@ -103,7 +128,7 @@ def monopole_accel(pos, mass, params, theta, min_level=2):
     while cnt[-1] > 1:
         cnt.append((cnt[-1] + 7) // 8)
     boxes_lo, boxes_hi, nmass, ncom = [llo.T.copy()], [lhi.T.copy()], [], []
-    lm = np.array([m_s[b:b + c].sum() for b, c in zip(lbeg, lcnt)])
+    lm = np.array([_seq_sum(m_s[b:b + c]) for b, c in zip(lbeg, lcnt)])
     lx = np.array([(m_s[b:b + c] * wpos[:, b:b + c]).sum(1) for b, c in zip(lbeg, lcnt)]).reshape(-1, 3)
     nmass.append(lm)
     ncom.append(lx)                      # sum of m x for now
@@ -116,7 +141,7 @@ def monopole_accel(pos, mass, params, theta, min_level=2):
             a, b = 8 * i, min(8 * i + 8, cnt[h - 1])
             lo[i] = boxes_lo[h - 1][a:b].min(0)
             hi[i] = boxes_hi[h - 1][a:b].max(0)
-            mm[i] = nmass[h - 1][a:b].sum()
+            mm[i] = _seq_sum(nmass[h - 1][a:b])
             mx[i] = ncom[h - 1][a:b].sum(0)
         boxes_lo.append(lo)
         boxes_hi.append(hi)
@@ -129,11 +154,18 @@ def monopole_accel(pos, mass, params, theta, min_level=2):
     n_mono = 0
     n_pp = 0
     ell2 = p.eps * p.eps
+    if alpha > 0:
+        ar = np.asarray(acc_ref, dtype=np.float64)[:, order]
+        amag2 = (ar[0] * ar[0] + ar[1] * ar[1]) + ar[2] * ar[2]
+    cell = L / float(W)
     for start, count, alo, ahi in _blocks(q, n, emax):
         mono, ppl = [], []
+        a2 = float(amag2[start:start + count].min()) if alpha > 0 else 0.0
 
         def visit(h, i, s):
-            if h >= min_level and _accept(alo, ahi, boxes_lo[h][i], boxes_hi[h][i], s, W, theta):
+            rel = (p.G, float(nmass[h][i]), cell, alpha, a2) if alpha > 0 else None
+            if h >= min_level and (theta > 0 or alpha > 0) and \
+                    _accept(alo, ahi, boxes_lo[h][i], boxes_hi[h][i], s, W, theta, rel):
                 mono.append((h, i, s))
                 return
             if h == 0:

@@ -73,6 +73,7 @@ _SIGS = {
     "pp_accel_f64": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
     "pp_plan_set_monopole": (_i32, [_P, C.c_double]),
+    "pp_plan_set_monopole_relative": (_i32, [_P, C.c_double, _P, _i64, _P]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
     "pp_plan_set_timing": (_i32, [_P, _i32]),
     "pp_plan_get_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
@@ -269,6 +270,17 @@ class Plan:
     def set_monopole(self, theta: float):
         """Monopole acceptance for accel (0 = exact pair sums)."""
         _check(_lib.pp_plan_set_monopole(self._h, float(theta)), "pp_plan_set_monopole")
+
+    def set_monopole_relative(self, alpha: float, acc_ref: torch.Tensor | None = None, stream=None):
+        """Gadget-2's relative opening test for accel against reference
+        accelerations acc_ref [3][n] (FP32, device); alpha = 0 turns it off."""
+        if alpha > 0:
+            n = acc_ref.shape[1]
+            ptr = _dev(acc_ref, torch.float32, (3, n), "acc_ref")
+        else:
+            n, ptr = 0, C.c_void_p(None)
+        _check(_lib.pp_plan_set_monopole_relative(self._h, float(alpha), ptr, n, _stream(stream)),
+               "pp_plan_set_monopole_relative")
 
     def get_tuning(self) -> dict:
         t = pp_tuning()

@@ -115,7 +115,10 @@ struct Batch {
     pp_tuning tune{2048, 1, 20, 0, 0, 1};
     int64_t graph_variant = -1;
     bool table_ready = false;      // the interpolated split table is built
-    double theta = 0.0;            // monopole acceptance (0: exact pair sums)
+    double theta = 0.0;            // geometric monopole acceptance (0: off)
+    double alpha = 0.0;            // relative monopole acceptance (0: off)
+    DevBuf acc_ref;                // FP32 [3][acc_ref_n]: its reference accelerations
+    int64_t acc_ref_n = 0;
     bool lists_mono = false;       // the current lists hold monopoles
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
@@ -205,9 +208,20 @@ struct Batch {
         PP_TRY(stage_trees(bd, w, s));
         // monopoles only on the FP32 path: the FP64 yardstick and the pair
         // count keep exact lists
-        const bool mono = mass_f != nullptr && theta > 0.0;
-        if (mono) PP_TRY(stage_node_moments(bd, w, s));
-        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mono ? theta * theta : 0.0));
+        MonoCfg mc;
+        if (mass_f != nullptr) {
+            mc.theta2 = theta * theta;
+            mc.alpha = alpha;
+            mc.acc_ref = acc_ref.as<float>();
+        }
+        const bool mono = mc.on();
+        if (mono && mc.alpha > 0.0 && acc_ref_n != N)
+            return fail(PP_EINVAL, "the reference accelerations were given for another particle count");
+        if (mono) {
+            PP_TRY(stage_node_moments(bd, w, s));
+            mc.mc = w.tree_mc.as<double4>();
+        }
+        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mc));
         lists_mono = mono;
         st.n = N;
         st.nleaf = w.nleaf;
@@ -726,6 +740,26 @@ int pp_plan_set_monopole(pp_plan* pl, double theta) {
     if (!(theta >= 0.0 && theta < 1.0)) return fail(PP_EINVAL, "theta must be in [0, 1)");
     pl->b.theta = theta;
     pl->b.lists_valid = false;
+    return PP_OK;
+}
+
+int pp_plan_set_monopole_relative(pp_plan* pl, double alpha, const float* acc_ref, int64_t n,
+                                  void* stream) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PP_EINVAL, "alpha must be finite and >= 0");
+    Batch& b = pl->b;
+    if (alpha > 0.0) {
+        if (!acc_ref) return fail(PP_EINVAL, "acc_ref is NULL");
+        if (n < 1 || n > b.n_max) return fail(PP_EINVAL, "n must be in 1..the plan's capacity");
+        PP_TRY(b.acc_ref.reserve(sizeof(float) * 3 * n));
+        PP_HIP(hipMemcpyAsync(b.acc_ref.p, acc_ref, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice,
+                              (hipStream_t)stream));
+        b.acc_ref_n = n;
+    } else {
+        b.acc_ref_n = 0;
+    }
+    b.alpha = alpha;
+    b.lists_valid = false;
     return PP_OK;
 }
 

@@ -150,6 +150,7 @@ struct Work {
     DevBuf mass_flag;        // int32 [nbox]: 1 where the box's FP32 masses are not all equal
     DevBuf split_tab;        // float4 [128]: the interpolated split table (variant bit 8)
     DevBuf tree_mc;          // double4 per tree node: sum m x, sum m y, sum m z, sum m
+    DevBuf blk_amin2;        // double per block: min |a_ref|^2 over its targets
     const FEntry* ent_final = nullptr;   // the list expansion's final entries (nentry)
     std::vector<int64_t> lvl_prefix_host;
     DevBuf sort_ws, scan_ws, sort_tmp;
@@ -203,9 +204,20 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
                  Work& w, hipStream_t s, const int* bad_dev = nullptr, int* bad_host = nullptr);
 int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);
-// theta2 > 0: monopole acceptance with theta^2 = theta2 (nodes of level >= 2)
+// Monopole acceptance settings of the list expansion (nodes of level >= 2):
+// every enabled test must hold.  theta2 = theta^2 of the geometric test
+// (0: off); alpha of Gadget-2's relative test against reference
+// accelerations acc_ref (FP32 [3][N], input order; 0: off).  mc: node
+// moments (stage_node_moments).
+struct MonoCfg {
+    double theta2 = 0.0;
+    double alpha = 0.0;
+    const double4* mc = nullptr;
+    const float* acc_ref = nullptr;
+    bool on() const { return theta2 > 0.0 || alpha > 0.0; }
+};
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s, double theta2 = 0.0);
+                hipStream_t s, const MonoCfg& mono = MonoCfg());
 // Mass and mass-weighted position sums of every tree node (after stage_trees;
 // needs the FP32 masses in key order).
 int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s);

@@ -295,26 +295,66 @@ __device__ __forceinline__ int64_t gap2_min(const IBox& A, const IBox& B, const 
     return r;
 }
 
-// Monopole acceptance of node box B for target box A under shift s
-// (sec. 3.4): (A + B) / R <= theta with A, B the longest box sides and R
-// the distance of the box centres, tested as (2 (A + B))^2 <= theta^2
-// (2R)^2 with 2R from integer half-cell coordinates.  Every operation is
-// exact except the two products on the right, so the decision does not
-// depend on the evaluation order of the caller.  (For theta < 1 it also
-// gives B / (R - A) <= theta.)
+// Monopole acceptance of the node of box B (global index g) for target box
+// A (block b) under shift s (sec. 3.4), every enabled test required:
+//  * geometric: (A + B) / R <= theta with A, B the longest box sides and R
+//    the distance of the box centres, tested as (2 (A + B))^2 <= theta^2
+//    (2R)^2 from integer half-cell coordinates (for theta < 1 this gives
+//    B / (R - A) <= theta too);
+//  * relative (Gadget-2, sec. 3.1): G M B^2 / r^4 <= alpha |a| with M the
+//    node mass, r the gap between the boxes and |a| the smallest reference
+//    acceleration of the block's targets, squared on both sides so that no
+//    root is taken.
+// Each side is a fixed sequence of FP64 operations on exact integers, the
+// node mass and the block's |a|^2, so the oracle can repeat the decision.
+struct MonoDev {
+    double theta2, alpha;
+    const double4* mc;
+    const double* amin2;
+};
+
 __device__ __forceinline__ bool accept_monopole(const IBox& A, const IBox& B, const int s[3], int64_t W,
-                                                double theta2) {
+                                                const MonoDev& M, int64_t g, int64_t b, double G,
+                                                double cell) {
 #pragma clang fp contract(off)
-    int64_t a = 0, b = 0, r2 = 0;
+    int64_t a = 0, bm = 0, r2 = 0;
     for (int ax = 0; ax < 3; ++ax) {
         const int64_t sa = (int64_t)A.hi[ax] - A.lo[ax], sb = (int64_t)B.hi[ax] - B.lo[ax];
         a = sa > a ? sa : a;
-        b = sb > b ? sb : b;
+        bm = sb > bm ? sb : bm;
         const int64_t d = ((int64_t)B.lo[ax] + B.hi[ax] + 2 * (int64_t)s[ax] * W) - ((int64_t)A.lo[ax] + A.hi[ax]);
         r2 += d * d;
     }
-    const double lhs = (double)(2 * (a + b));
-    return lhs * lhs <= theta2 * (double)r2;
+    if (M.theta2 > 0.0) {
+        const double lhs = (double)(2 * (a + bm));
+        if (!(lhs * lhs <= M.theta2 * (double)r2)) return false;
+    }
+    if (M.alpha > 0.0) {
+        const int64_t gap2 = gap2_shift(A, B, s, W);
+        const double bc = (double)bm * cell;
+        const double lhs = ((G * M.mc[g].w) * bc) * bc;
+        const double g2 = ((double)gap2 * cell) * cell;
+        const double rhs2 = ((M.alpha * M.alpha) * M.amin2[b]) * ((g2 * g2) * (g2 * g2));
+        if (!(lhs * lhs <= rhs2)) return false;
+    }
+    return true;
+}
+
+// Smallest |a_ref|^2 over each block's targets (a_ref in input order).
+__global__ void block_amin_kernel(const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
+                                  const int32_t* __restrict__ perm, const float* __restrict__ acc_ref,
+                                  int64_t N, int64_t nb, double* __restrict__ amin2) {
+#pragma clang fp contract(off)
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double m = 0.0;
+    for (int32_t k = 0; k < bcount[b]; ++k) {
+        const int64_t i = perm[(int64_t)bstart[b] + k];
+        const double x = (double)acc_ref[i], y = (double)acc_ref[N + i], z = (double)acc_ref[2 * N + i];
+        const double v = ((x * x) + (y * y)) + (z * z);
+        m = k == 0 || v < m ? v : m;
+    }
+    amin2[b] = m;
 }
 
 // ------------------------------------------------------- canonical list --
@@ -539,7 +579,7 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                 const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                 const int32_t* __restrict__ bboxid, int64_t nb,
                                 int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                FEntry* __restrict__ out, double theta2) {
+                                FEntry* __restrict__ out, MonoDev mono) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int x = bboxid[b];
@@ -564,7 +604,8 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
             e.sc = (uint8_t)sc;
             e.lev = (uint8_t)top;
             e.inside = maxd2_shift(A, R, s, W) < T;
-            e.mono = theta2 > 0.0 && top >= kMonoMinLevel && accept_monopole(A, R, s, W, theta2);
+            e.mono = (mono.theta2 > 0.0 || mono.alpha > 0.0) && top >= kMonoMinLevel &&
+                     accept_monopole(A, R, s, W, mono, tv.off[top], b, bd.box[x].G, bd.box[x].cell);
             out[o++] = e;
         } else {
             ++c;
@@ -581,13 +622,14 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                  const int32_t* __restrict__ bboxid, const FEntry* __restrict__ in,
                                  int64_t F, int stop, int32_t* __restrict__ cnt,
                                  const int64_t* __restrict__ off, FEntry* __restrict__ out,
-                                 double theta2) {
+                                 MonoDev mono) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= F) return;
     const FEntry E = in[e];
     // with monopole acceptance, inside entries are opened too (a child may
     // be accepted); accepted entries are final
-    if (E.mono || E.lev <= stop || (E.inside && theta2 == 0.0)) {
+    const bool mono_on = mono.theta2 > 0.0 || mono.alpha > 0.0;
+    if (E.mono || E.lev <= stop || (E.inside && !mono_on)) {
         if (FILL) out[off[e]] = E;
         else cnt[e] = 1;
         return;
@@ -611,8 +653,9 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
         C.sc = E.sc;
         C.lev = (uint8_t)(E.lev - 1);
         C.inside = (inside >> c) & 1u;
-        C.mono = theta2 > 0.0 && C.lev >= kMonoMinLevel &&
-                 accept_monopole(bbox[E.blk], nodes[tvs[x].off[C.lev] + C.node], s, bd.box[x].W, theta2);
+        C.mono = mono_on && C.lev >= kMonoMinLevel &&
+                 accept_monopole(bbox[E.blk], nodes[tvs[x].off[C.lev] + C.node], s, bd.box[x].W, mono,
+                                 tvs[x].off[C.lev] + C.node, E.blk, bd.box[x].G, bd.box[x].cell);
         out[o++] = C;
     }
 }
@@ -950,7 +993,7 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
 }
 
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s, double theta2) {
+                hipStream_t s, const MonoCfg& mcfg) {
     const int nbox = bd.nbox;
     const int64_t N = poff[nbox];
     w.nblock = w.nentry = w.nrange = w.nitem = w.candidates = 0;
@@ -993,6 +1036,15 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     const IBox* nodes = w.tree_boxes.as<IBox>();
     const IBox* bbox = w.bbox.as<IBox>();
     const int32_t* bboxid = w.bboxid.as<int32_t>();
+    MonoDev mono{mcfg.theta2, mcfg.alpha, mcfg.mc, nullptr};
+    if (mcfg.alpha > 0.0) {
+        PP_TRY(w.blk_amin2.reserve(sizeof(double) * (nb + 1)));
+        hipLaunchKernelGGL(block_amin_kernel, dim3(blocks_for(nb, 128)), dim3(128), 0, s,
+                           w.bstart.as<int32_t>(), w.bcount.as<int32_t>(), w.perm.as<int32_t>(),
+                           mcfg.acc_ref, w.pos_n, nb, w.blk_amin2.as<double>());
+        PP_HIP(hipGetLastError());
+        mono.amin2 = w.blk_amin2.as<double>();
+    }
     // breadth-first from every box's root down to the DFS level
     DevBuf* cur = &w.fent_a;
     DevBuf* nxt = &w.fent_b;
@@ -1001,14 +1053,14 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.foff.reserve(sizeof(int64_t) * (nb + 2)));
     hipLaunchKernelGGL(bfs_root_kernel<false>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, nb, w.fcnt.as<int32_t>(), (const int64_t*)nullptr,
-                       (FEntry*)nullptr, theta2);
+                       (FEntry*)nullptr, mono);
     PP_HIP(hipGetLastError());
     PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), nb, w.scan_ws, s));
     PP_TRY(read_back(w.foff.as<int64_t>() + nb, &F, s));
     PP_TRY(cur->reserve(sizeof(FEntry) * (F + 1)));
     hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, nb, (int32_t*)nullptr, w.foff.as<int64_t>(),
-                       cur->as<FEntry>(), theta2);
+                       cur->as<FEntry>(), mono);
     PP_HIP(hipGetLastError());
     // Levels above kDfsLevel must be expanded (the masks cover 64 leaves);
     // level 2 -> 1 is taken too when the expanded entries fit the budget.
@@ -1019,7 +1071,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         PP_TRY(w.foff.reserve(sizeof(int64_t) * (F + 2)));
         hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd,
                            tvs, nodes, bbox, bboxid, cur->as<FEntry>(), F, stop,
-                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr, theta2);
+                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr, mono);
         PP_HIP(hipGetLastError());
         PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), F, w.scan_ws, s));
         int64_t F2 = 0;
@@ -1028,7 +1080,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         PP_TRY(nxt->reserve(sizeof(FEntry) * (F2 + 1)));
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                            nodes, bbox, bboxid, cur->as<FEntry>(), F, stop, (int32_t*)nullptr,
-                           w.foff.as<int64_t>(), nxt->as<FEntry>(), theta2);
+                           w.foff.as<int64_t>(), nxt->as<FEntry>(), mono);
         PP_HIP(hipGetLastError());
         DevBuf* t = cur;
         cur = nxt;

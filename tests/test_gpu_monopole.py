@@ -87,3 +87,47 @@ def test_monopole_mode_keeps_f64_exact_and_refuses_counts(pp, box, oracle_mod):
     assert tot == int(ref["n_inter"].sum())
     with pytest.raises(pp.PPError):
         plan.set_monopole(1.0)
+
+
+@pytest.fixture(scope="module")
+def box_ref(box, oracle_mod):
+    pos, mass, p = box
+    return oracle_mod.accel(pos, mass.astype(np.float64), p)["acc"]
+
+
+@pytest.mark.parametrize("theta,alpha", [(0.0, 0.005), (0.5, 0.02)])
+def test_relative_criterion_matches_tree_oracle(pp, box, box_ref, theta, alpha):
+    """Gadget-2's relative test against reference accelerations (here the
+    exact ones, rounded to FP32 as the caller would pass them)."""
+    from oracle import tree
+    pos, mass, p = box
+    acc_ref = box_ref.astype(np.float32)
+    ref = tree.monopole_accel(pos, mass.astype(np.float64), p, theta, alpha=alpha, acc_ref=acc_ref)
+    plan = pp.Plan(p, pos.shape[1])
+    plan.set_monopole(theta)
+    plan.set_monopole_relative(alpha, dev(acc_ref, torch.float32))
+    acc = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    st = plan.stats()
+    assert st["monopoles"] == ref["n_mono_pairs"] > 0, (st["monopoles"], ref["n_mono_pairs"])
+    e = rel(acc, ref["acc"])
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99.9) <= 1e-4, (np.median(e), np.percentile(e, 99.9))
+    # switching the relative test off again restores the exact sums
+    plan.set_monopole(0.0)
+    plan.set_monopole_relative(0.0)
+    plan.accel(dev(pos, torch.float64), dev(mass, torch.float32))
+    assert plan.stats()["monopoles"] == 0
+
+
+def test_relative_criterion_argument_errors(pp, box):
+    pos, mass, p = box
+    n = pos.shape[1]
+    plan = pp.Plan(p, n)
+    ref = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(pp.PPError):
+        plan.set_monopole_relative(-1.0, ref)
+    with pytest.raises(pp.PPError):
+        plan.set_monopole_relative(float("nan"), ref)
+    # reference accelerations for fewer particles than the call has
+    plan.set_monopole_relative(0.01, ref[:, : n // 2].contiguous())
+    with pytest.raises(pp.PPError):
+        plan.accel(dev(pos, torch.float64), dev(mass, torch.float32))
