@@ -122,7 +122,20 @@ def cpu_baseline(box, acc_gpu, budget_s):
             "kind": "oracle",
             "sample": f"{k} seeded random targets of the same box against all {box.n} sources "
                       f"(FP64 direct sum, {inter} interactions, {sec:.1f} s)"}
-    return base, sample_errors(acc_gpu, targets, ref), targets, ref
+    errs = sample_errors(acc_gpu, targets, ref)
+    # condition-robust error |a - a*| / sum_j |a_ij| on every 8th sampled
+    # target (a second, untimed oracle call that also sums the pair magnitudes)
+    sub = targets[::8]
+    rs = oracle.accel(box.pos, mass64, box.params, targets=sub, pair_abs=True)
+    a = acc_gpu[:, sub].astype(np.float64)
+    r = rs["acc"]
+    cands = [r, r - rs["band_in"] + rs["band_out"], r - rs["band_in"], r + rs["band_out"]]
+    d = np.min([np.linalg.norm(a - c, axis=0) for c in cands], axis=0)
+    has = rs["n_inter"] > 0
+    e = d[has] / rs["pair_abs"][has]
+    errs["robust"] = {"targets": int(has.sum()), "p999": nearest_rank(e, 99.9),
+                      "max": float(e.max()) if e.size else 0.0}
+    return base, errs, targets, ref
 
 
 def sample_errors(acc_gpu, targets, ref):

@@ -39,7 +39,7 @@ def _load():
     lib.oracle_split_factor.argtypes = [dbl]
     lib.oracle_num_threads.restype = i32
     lib.oracle_accel.restype = i32
-    lib.oracle_accel.argtypes = [P, P, i64, dbl, dbl, dbl, dbl, dbl, P, i64, P, P, P, P, P]
+    lib.oracle_accel.argtypes = [P, P, i64, dbl, dbl, dbl, dbl, dbl, P, i64, P, P, P, P, P, P]
     lib.oracle_hilbert_keys.restype = i32
     lib.oracle_hilbert_keys.argtypes = [P, i64, dbl, i32, P]
     lib.oracle_hilbert_decode.restype = None
@@ -71,12 +71,14 @@ def split_factor(x) -> np.ndarray:
     return np.array([lib.oracle_split_factor(float(v)) for v in xs])
 
 
-def accel(pos, mass, params, targets=None):
+def accel(pos, mass, params, targets=None, pair_abs=False):
     """Direct FP64 short-range sum.
 
     pos: float64 [3, n]; mass: [n]; params: object with L, rs, rcut, eps, G.
     targets: optional int64 indices.  Returns dict with 'acc' [3, nt],
-    'band_in', 'band_out' [3, nt], 'n_inter' [nt], 'n_band' [nt].
+    'band_in', 'band_out' [3, nt], 'n_inter' [nt], 'n_band' [nt], and with
+    pair_abs, 'pair_abs' [nt]: the sum over the kept pairs of the pair
+    accelerations' magnitudes (the scale of the condition-robust error).
     """
     lib = _load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -92,11 +94,16 @@ def accel(pos, mass, params, targets=None):
     bo = np.zeros((3, nt))
     ni = np.zeros(nt, dtype=np.int64)
     nb = np.zeros(nt, dtype=np.int64)
+    pa = np.zeros(nt) if pair_abs else None
     rc = lib.oracle_accel(_p(pos), _p(mass), n, params.L, params.rs, params.rcut, params.eps,
-                          params.G, tp, nt, _p(acc), _p(bi), _p(bo), _p(ni), _p(nb))
+                          params.G, tp, nt, _p(acc), _p(bi), _p(bo), _p(ni), _p(nb),
+                          _p(pa) if pair_abs else None)
     if rc != 0:
         raise ValueError(f"oracle_accel failed ({rc})")
-    return {"acc": acc, "band_in": bi, "band_out": bo, "n_inter": ni, "n_band": nb}
+    out = {"acc": acc, "band_in": bi, "band_out": bo, "n_inter": ni, "n_band": nb}
+    if pair_abs:
+        out["pair_abs"] = pa
+    return out
 
 
 def quantise(pos, L, bits=21) -> np.ndarray:

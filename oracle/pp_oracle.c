@@ -111,7 +111,7 @@ int oracle_accel(const double* pos, const double* mass, int64_t n,
                  double L, double rs, double rcut, double eps, double G,
                  const int64_t* targets, int64_t nt,
                  double* acc, double* band_in, double* band_out,
-                 int64_t* n_inter, int64_t* n_band)
+                 int64_t* n_inter, int64_t* n_band, double* pair_abs)
 {
     if (n < 0 || nt < 0 || !(L > 0) || !(rs > 0) || !(rcut > 0) || !(rcut < 0.5 * L) || !(eps >= 0))
         return ORACLE_EINVAL;
@@ -132,6 +132,7 @@ int oracle_accel(const double* pos, const double* mass, int64_t n,
         nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
         nsum bix = {0, 0}, biy = {0, 0}, biz = {0, 0};
         nsum box = {0, 0}, boy = {0, 0}, boz = {0, 0};
+        nsum sab = {0, 0};
         int64_t kept = 0, nb = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
@@ -151,6 +152,7 @@ int oracle_accel(const double* pos, const double* mass, int64_t n,
             if (keep) {
                 ++kept;
                 nsum_add(&ax, fx); nsum_add(&ay, fy); nsum_add(&az, fz);
+                if (pair_abs) nsum_add(&sab, sqrt(fx * fx + fy * fy + fz * fz));
                 if (in_band) { nsum_add(&bix, fx); nsum_add(&biy, fy); nsum_add(&biz, fz); }
             } else {
                 nsum_add(&box, fx); nsum_add(&boy, fy); nsum_add(&boz, fz);
@@ -164,6 +166,7 @@ int oracle_accel(const double* pos, const double* mass, int64_t n,
         if (band_out) { band_out[t] = nsum_get(&box); band_out[nt + t] = nsum_get(&boy); band_out[2 * nt + t] = nsum_get(&boz); }
         if (n_inter) n_inter[t] = kept;
         if (n_band) n_band[t] = nb;
+        if (pair_abs) pair_abs[t] = nsum_get(&sab);
     }
     free(w);
     return ORACLE_OK;

@@ -132,7 +132,7 @@ def test_near_pairs_bit_exact(pp, oracle_mod, case):
 @pytest.fixture(scope="module")
 def cfg1_ref(oracle_mod):
     b = W.make_config(1)
-    return b, oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params)
+    return b, oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, pair_abs=True)
 
 
 def test_accel_f32_cfg1_full(pp, cfg1_ref):
@@ -144,6 +144,7 @@ def test_accel_f32_cfg1_full(pp, cfg1_ref):
     assert s["zero_ok"]
     assert s["median"] <= 1e-6
     assert s["p999"] <= 1e-4
+    assert s["robust_max"] <= parity.ROBUST_MAX
 
 
 def test_accel_f64_cfg1_full(pp, cfg1_ref):
@@ -198,16 +199,19 @@ def test_accel_edge_cases(pp, oracle_mod, case):
     mass = np.random.default_rng(n).uniform(0.5, 1.5, n).astype(np.float32)
     if case == "lattice":
         mass[:] = 1.0                      # a lattice is force-free only with equal masses
-    ref = oracle_mod.accel(pos, mass.astype(np.float64), p)
+    ref = oracle_mod.accel(pos, mass.astype(np.float64), p, pair_abs=True)
     plan = pp.Plan(p, n + 10)
     acc = plan.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
     if case == "lattice":
         unit = 1.0 / (p.L / 8) ** 2
         assert np.abs(acc).max() < 1e-5 * unit
+        # the forces cancel exactly: only the condition-robust error is defined
+        assert parity.robust_errors(acc, ref).max() <= parity.ROBUST_MAX
         return
     s = parity.summary(acc, ref)
     assert s["zero_ok"], case
     assert s["median"] <= 1e-6 and s["p999"] <= 1e-4, (case, s)
+    assert s["robust_max"] <= parity.ROBUST_MAX, (case, s)
     a64 = plan.accel_f64(dev(pos, torch.float64), dev(mass.astype(np.float64), torch.float64)).cpu().numpy()
     s64 = parity.summary(a64, ref)
     assert s64["max"] <= 1e-10, (case, s64)
@@ -228,7 +232,7 @@ def cfg2_sample(oracle_mod):
     b = W.make_config(2)
     rng = np.random.default_rng(2024)
     targets = np.sort(rng.choice(b.n, 1536, replace=False))
-    ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, targets=targets)
+    ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, targets=targets, pair_abs=True)
     return b, targets, ref
 
 
@@ -239,6 +243,7 @@ def test_accel_f32_cfg2_sampled(pp, cfg2_sample):
     s = parity.summary(acc, ref)
     print("cfg2 f32 sampled", s, plan.stats())
     assert s["median"] <= 1e-6 and s["p999"] <= 1e-4
+    assert s["robust_max"] <= parity.ROBUST_MAX
     tot, counts = plan.count_interactions(per_target=True)
     assert np.array_equal(counts.cpu().numpy()[targets], ref["n_inter"])
 

@@ -15,7 +15,10 @@ What fixes each property (none of them is a retyped copy of the oracle):
   * reduction to a textbook routine: with r_s -> infinity and r_cut just
     under L/2 the sum is the minimum-image Plummer direct sum, computed here
     by a separate vectorised numpy loop;
-  * pair counts equal a numpy brute-force count.
+  * pair counts equal a numpy brute-force count;
+  * the pair-magnitude sum (the scale of the condition-robust error) is
+    |a| for two bodies, twice one pair's magnitude for a target midway
+    between two equal masses (whose force cancels), and never below |a|.
 """
 import math
 
@@ -186,3 +189,29 @@ def test_rejects_cut_beyond_half_box(oracle_mod):
     p = BoxParams(L=10.0, rs=1.0, rcut=5.0, eps=0.0)
     with pytest.raises(ValueError):
         oracle_mod.accel(np.zeros((3, 2)), np.ones(2), p)
+
+
+def test_pair_magnitude_sum(oracle_mod):
+    p = P()
+    rng = np.random.default_rng(5)
+    # two bodies: the sum over one pair is that pair's |a|
+    pos = np.array([[3.0, 3.0 + 1.1], [4.0, 4.2], [5.0, 4.7]])
+    mass = np.array([0.7, 1.9])
+    r = oracle_mod.accel(pos, mass, p, pair_abs=True)
+    for k in range(2):
+        ref = two_body_ref(pos[:, 1 - k] - pos[:, k], mass[1 - k], p)
+        assert r["pair_abs"][k] == pytest.approx(np.linalg.norm(ref), rel=1e-13)
+    # a target midway between two equal masses: no force, twice one pair
+    pos = np.array([[4.0, 5.0, 6.0], [5.0, 5.0, 5.0], [5.0, 5.0, 5.0]])
+    r = oracle_mod.accel(pos, np.ones(3), p, pair_abs=True)
+    one = np.linalg.norm(two_body_ref(np.array([1.0, 0.0, 0.0]), 1.0, p))
+    assert np.abs(r["acc"][:, 1]).max() <= 1e-15 * one
+    assert r["pair_abs"][1] == pytest.approx(2 * one, rel=1e-13)
+    # triangle inequality on a random box; zero without neighbours
+    pos = rng.uniform(0, p.L, (3, 300))
+    pos[:, 0] = [0.5 * p.L] * 3
+    pos[:, 1:] = np.where(np.linalg.norm(pos[:, 1:] - pos[:, :1], axis=0) < 1.05 * p.rcut,
+                          np.mod(pos[:, 1:] + 0.5 * p.L, p.L), pos[:, 1:])
+    r = oracle_mod.accel(pos, rng.uniform(0.5, 2.0, 300), p, pair_abs=True)
+    assert np.all(r["pair_abs"] >= np.linalg.norm(r["acc"], axis=0) * (1 - 1e-14))
+    assert np.all((r["pair_abs"] > 0) == (r["n_inter"] > 0))
