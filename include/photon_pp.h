@@ -152,6 +152,18 @@ void pp_plan_destroy(pp_plan* plan);
 int pp_accel(pp_plan* plan, const double* pos, const float* mass, int64_t n, float* acc,
              void* stream);
 
+/* pp_accel for the targets whose flag active[i] (device uint8 [n], input
+ * order) is non-zero; acc[:, i] of the other targets is not written.  All n
+ * particles are sources.  The active targets get exactly pp_accel's values
+ * (the same lists, work items and summation order); the work saved is that
+ * of the 64-particle target blocks (in key order) without an active target.
+ * This is the force evaluation of the block time steps of sec. 3.4, where
+ * only the particles whose step ends need new forces.  Synchronises the
+ * stream like pp_accel.  pp_count_interactions refuses lists built by this
+ * call (PP_EINVAL).  Errors as pp_accel, and PP_EINVAL for a NULL active
+ * with n > 0. */
+int pp_accel_active(pp_plan* plan, const double* pos, const float* mass, int64_t n,
+                    const uint8_t* active, float* acc, void* stream);
 /* The same sum entirely in FP64 (accuracy yardstick).                     */
 int pp_accel_f64(pp_plan* plan, const double* pos, const double* mass, int64_t n, double* acc,
                  void* stream);
@@ -308,8 +320,9 @@ void pp_pm_plan_destroy(pp_pm_plan* plan);
  * (the Gadget-2 criterion that sec. 3.4 follows).  Levels are set from the
  * forces at the start of a top step.  A top step runs 2^K substeps (K the
  * deepest level in use): opening half kicks where a particle's step starts,
- * a drift of all particles, the forces (for all particles), closing half
- * kicks where a step ends.
+ * a drift of all particles, the forces, closing half kicks where a step
+ * ends.  The short-range force is evaluated for the particles whose step
+ * ends at the substep only (pp_accel_active), the PM force for all.
  *
  * pp_kdk_create: p as for pp_plan_create, with eps > 0 (it enters the step
  *   criterion); n particles; eta > 0; 0 <= max_level <= 15.  The object owns
@@ -329,6 +342,8 @@ typedef struct pp_kdk_info {
     int64_t top_steps;           /* pp_kdk_step calls */
     int64_t force_evaluations;   /* including the one of pp_kdk_init */
     int64_t level_count[16];     /* particles per level in the last top step */
+    int64_t short_range_targets; /* targets given new short-range forces, summed
+                                    over the force evaluations */
 } pp_kdk_info;
 int pp_kdk_create(const pp_box_params* p, int32_t n_mesh, int64_t n, double eta, int32_t max_level,
                   pp_kdk** out);

@@ -73,6 +73,7 @@ _SIGS = {
     "pp_accel_f64": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
     "pp_plan_set_monopole": (_i32, [_P, C.c_double]),
+    "pp_accel_active": (_i32, [_P, _P, _P, _i64, _P, _P, _P]),
     "pp_plan_set_monopole_relative": (_i32, [_P, C.c_double, _P, _i64, _P]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
     "pp_plan_set_timing": (_i32, [_P, _i32]),
@@ -246,6 +247,18 @@ class Plan:
         _check(_lib.pp_accel(self._h, _dev(pos, torch.float64, (3, n), "pos"),
                              _dev(mass, torch.float32, (n,), "mass"), n,
                              _dev(out, torch.float32, (3, n), "acc"), _stream(stream)), "pp_accel")
+        return out
+
+    def accel_active(self, pos: torch.Tensor, mass: torch.Tensor, active: torch.Tensor,
+                     out: torch.Tensor, stream=None) -> torch.Tensor:
+        """accel for the targets with active[i] != 0 (uint8 [n]); the other
+        columns of out are left as they were."""
+        n = pos.shape[1]
+        _check(_lib.pp_accel_active(self._h, _dev(pos, torch.float64, (3, n), "pos"),
+                                    _dev(mass, torch.float32, (n,), "mass"), n,
+                                    _dev(active, torch.uint8, (n,), "active"),
+                                    _dev(out, torch.float32, (3, n), "acc"), _stream(stream)),
+               "pp_accel_active")
         return out
 
     def accel_f64(self, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
@@ -425,7 +438,8 @@ def pp_pm_plan_create(params, n_mesh: int) -> PMPlan:
 
 class pp_kdk_info(C.Structure):
     _fields_ = [("deepest_level", C.c_int32), ("pad", C.c_int32), ("top_steps", C.c_int64),
-                ("force_evaluations", C.c_int64), ("level_count", C.c_int64 * 16)]
+                ("force_evaluations", C.c_int64), ("level_count", C.c_int64 * 16),
+                ("short_range_targets", C.c_int64)]
 
 
 class KDK:
@@ -455,7 +469,8 @@ class KDK:
         i = pp_kdk_info()
         _check(_lib.pp_kdk_get_info(self._h, C.byref(i)), "pp_kdk_get_info")
         return {"deepest_level": i.deepest_level, "top_steps": i.top_steps,
-                "force_evaluations": i.force_evaluations, "level_count": list(i.level_count)}
+                "force_evaluations": i.force_evaluations, "level_count": list(i.level_count),
+                "short_range_targets": i.short_range_targets}
 
     def levels(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n, dtype=torch.int8, device="cuda")

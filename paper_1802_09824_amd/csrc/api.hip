@@ -120,6 +120,7 @@ struct Batch {
     DevBuf acc_ref;                // FP32 [3][acc_ref_n]: its reference accelerations
     int64_t acc_ref_n = 0;
     bool lists_mono = false;       // the current lists hold monopoles
+    bool lists_active = false;     // the current items cover the active targets only
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
     bool timing = false, timed = false;
@@ -131,6 +132,7 @@ struct Batch {
     hipStream_t cap_stream = nullptr;     // capture only (the null stream cannot be captured)
     uint64_t graph_gen = 0;
     const void* graph_acc = nullptr;
+    const void* graph_active = nullptr;
 
     ~Batch() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -187,7 +189,8 @@ struct Batch {
 
     // Stages shared by every entry point: keys, sort, gather, leaves, trees,
     // block lists.  Synchronises the stream.
-    int prepare(const double* pos, const float* mass_f, const double* mass_d, hipStream_t s) {
+    int prepare(const double* pos, const float* mass_f, const double* mass_d, hipStream_t s,
+                const uint8_t* active = nullptr) {
         lists_valid = false;
         evaluated_valid = false;
         w.pos_n = N;
@@ -221,8 +224,9 @@ struct Batch {
             PP_TRY(stage_node_moments(bd, w, s));
             mc.mc = w.tree_mc.as<double4>();
         }
-        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mc));
+        PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mc, active));
         lists_mono = mono;
+        lists_active = active != nullptr;
         st.n = N;
         st.nleaf = w.nleaf;
         st.nblock = w.nblock;
@@ -280,6 +284,7 @@ struct Batch {
         PP_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         graph_gen = alloc_generation();
         graph_acc = acc;
+        graph_active = w.active;
         graph_variant = graph_key();
         return PP_OK;
     }
@@ -293,7 +298,7 @@ struct Batch {
         PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.nitem + 1)));
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
-                graph_variant != graph_key())
+                graph_active != w.active || graph_variant != graph_key())
                 PP_TRY(capture(acc));
             if (timing) PP_HIP(hipEventRecord(ev0, s));
             PP_HIP(hipGraphLaunch(gexec, s));
@@ -716,6 +721,17 @@ int pp_accel(pp_plan* pl, const double* pos, const float* mass, int64_t n, float
     return pl->b.run_f32(acc, s);
 }
 
+int pp_accel_active(pp_plan* pl, const double* pos, const float* mass, int64_t n,
+                    const uint8_t* active, float* acc, void* stream) {
+    PP_TRY(check_accel_args(pl, pos, mass, n, acc));
+    PP_TRY(check_ptr(active, n, "active"));
+    if (n == 0) return PP_OK;
+    PP_TRY(plan_resize(pl, n));
+    hipStream_t s = S(stream);
+    PP_TRY(pl->b.prepare(pos, mass, nullptr, s, active));
+    return pl->b.run_f32(acc, s);
+}
+
 int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, double* acc,
                  void* stream) {
     PP_TRY(check_accel_args(pl, pos, mass, n, acc));
@@ -791,6 +807,8 @@ static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStre
     if (!b.lists_valid) return fail(PP_EINVAL, "no lists: call the accel function first");
     if (b.lists_mono)
         return fail(PP_EINVAL, "the lists hold monopoles: count after pp_accel_f64 or with theta 0");
+    if (b.lists_active)
+        return fail(PP_EINVAL, "the lists cover the active targets only: count after pp_accel or pp_accel_f64");
     PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.nitem + 1)));
     PP_TRY(launch_count(b.bd, b.w, b.w.chunk, b.pcount.as<int32_t>(), s));
     unsigned long long* tot = b.w.misc.as<unsigned long long>() + 4;

@@ -8,9 +8,13 @@
 // dt / 2^K (K the deepest level in use): opening half kicks for the
 // particles whose step starts at the substep, a drift of every particle, the
 // forces at the new positions, closing half kicks for the particles whose
-// step ends there.  Forces are evaluated for all particles at every
-// substep (the lists are target-major, so a subset would need its own
-// lists); only the active particles' kicks use them.
+// step ends there.  Only those particles need new forces: the short-range
+// force is evaluated for them alone (pp_accel_active: the target blocks
+// without such a particle are skipped), from all particles as sources; the
+// PM force, one mesh solve for everybody, is evaluated in full.  A particle's
+// force is therefore fresh whenever a kick uses it: its closing kick
+// follows its own evaluation, and its next opening kick uses that same
+// force.
 #include <cmath>
 #include <new>
 
@@ -71,6 +75,14 @@ __global__ void __launch_bounds__(256) drift_kernel(double* __restrict__ pos, co
     pos[i] = x - L * floor(x / L);
 }
 
+// Flags the particles whose step ends at substep boundary s of 2^K.
+__global__ void __launch_bounds__(256) active_kernel(const int8_t* __restrict__ level, int64_t n, int K,
+                                                     int s, uint8_t* __restrict__ active) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    active[i] = (s % (1 << (K - level[i]))) == 0 ? 1 : 0;
+}
+
 __global__ void zero_i32_kernel(int32_t* __restrict__ p, int n) {
     const int i = threadIdx.x;
     if (i < n) p[i] = 0;
@@ -88,17 +100,24 @@ struct pp_kdk {
     int max_level = 0;
     pp_plan* plan = nullptr;
     pp_pm_plan* pm = nullptr;
-    DevBuf acc_pp, acc_pm, level, hist;
+    DevBuf acc_pp, acc_pm, level, hist, active;
     bool ready = false;
     pp_kdk_info info{};
     ~pp_kdk() {
         if (plan) pp_plan_destroy(plan);
         if (pm) pp_pm_plan_destroy(pm);
     }
-    int forces(const double* pos, const float* mass, hipStream_t s) {
-        PP_TRY(pp_accel(plan, pos, mass, n, acc_pp.as<float>(), (void*)s));
+    // active: per-particle flags of the targets that need new short-range
+    // forces (null: all); n_active of them
+    int forces(const double* pos, const float* mass, hipStream_t s, const uint8_t* act,
+               int64_t n_active) {
+        if (act)
+            PP_TRY(pp_accel_active(plan, pos, mass, n, act, acc_pp.as<float>(), (void*)s));
+        else
+            PP_TRY(pp_accel(plan, pos, mass, n, acc_pp.as<float>(), (void*)s));
         if (pm) PP_TRY(pp_pm_accel(pm, pos, mass, n, acc_pm.as<float>(), (void*)s));
         info.force_evaluations += 1;
+        info.short_range_targets += n_active;
         return PP_OK;
     }
 };
@@ -126,6 +145,7 @@ int pp_kdk_create(const pp_box_params* p, int32_t n_mesh, int64_t n, double eta,
     if (rc == PP_OK) rc = k->acc_pp.reserve(sizeof(float) * 3 * n);
     if (rc == PP_OK && k->pm) rc = k->acc_pm.reserve(sizeof(float) * 3 * n);
     if (rc == PP_OK) rc = k->level.reserve(n);
+    if (rc == PP_OK) rc = k->active.reserve(n);
     if (rc == PP_OK) rc = k->hist.reserve(sizeof(int32_t) * (kMaxKdkLevel + 1));
     if (rc != PP_OK) {
         delete k;
@@ -137,7 +157,7 @@ int pp_kdk_create(const pp_box_params* p, int32_t n_mesh, int64_t n, double eta,
 
 int pp_kdk_init(pp_kdk* k, const double* pos, const float* mass, void* stream) {
     if (!k || !pos || !mass) return fail(PP_EINVAL, "NULL argument");
-    PP_TRY(k->forces(pos, mass, (hipStream_t)stream));
+    PP_TRY(k->forces(pos, mass, (hipStream_t)stream, nullptr, k->n));
     k->ready = true;
     return PP_OK;
 }
@@ -167,13 +187,22 @@ int pp_kdk_step(pp_kdk* k, double* pos, double* vel, const float* mass, double d
     k->info.deepest_level = K;
     const int nsub = 1 << K;
     const double hsub = dt / (double)nsub;
+    uint8_t* act = k->active.as<uint8_t>();
     for (int sub = 0; sub < nsub; ++sub) {
         hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, vel, a1, a2, lev, n, K,
                            sub, dt);
         hipLaunchKernelGGL(drift_kernel, dim3(blocks_for(3 * n, 256)), dim3(256), 0, s, pos, vel, 3 * n,
                            hsub, k->p.L);
+        // the particles whose step ends at sub + 1 (all of them at the last one)
+        int64_t n_active = 0;
+        for (int l = 0; l <= K; ++l)
+            if ((sub + 1) % (1 << (K - l)) == 0) n_active += h[l];
+        const bool all = n_active == n;
+        if (!all)
+            hipLaunchKernelGGL(active_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, lev, n, K, sub + 1,
+                               act);
         PP_HIP(hipGetLastError());
-        PP_TRY(k->forces(pos, mass, s));
+        PP_TRY(k->forces(pos, mass, s, all ? nullptr : act, n_active));
         hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, vel, a1, a2, lev, n, K,
                            sub + 1, dt);
         PP_HIP(hipGetLastError());

@@ -152,6 +152,7 @@ struct Work {
     DevBuf tree_mc;          // double4 per tree node: sum m x, sum m y, sum m z, sum m
     DevBuf blk_amin2;        // double per block: min |a_ref|^2 over its targets
     const FEntry* ent_final = nullptr;   // the list expansion's final entries (nentry)
+    const uint8_t* active = nullptr;     // the items' target flags (null: every target)
     std::vector<int64_t> lvl_prefix_host;
     DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
@@ -216,8 +217,10 @@ struct MonoCfg {
     const float* acc_ref = nullptr;
     bool on() const { return theta2 > 0.0 || alpha > 0.0; }
 };
+// active: optional device flags per input particle; target blocks without an
+// active target get no work items (their outputs are left alone).
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s, const MonoCfg& mono = MonoCfg());
+                hipStream_t s, const MonoCfg& mono = MonoCfg(), const uint8_t* active = nullptr);
 // Mass and mass-weighted position sums of every tree node (after stage_trees;
 // needs the FP32 masses in key order).
 int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s);

@@ -49,8 +49,13 @@ struct ItemArgs {
     const int32_t* mass_flag;  // per box: 1 where the masses are not all equal
     const float4* split_tab;   // the interpolated split table (variant bit 8)
     float* acc;                // FP32 output (single-item blocks write it directly)
+    const uint8_t* active;     // per input particle: outputs written only where set (null: all)
     int chunk;
 };
+
+__device__ __forceinline__ bool target_on(const ItemArgs& ia, int64_t i) {
+    return !ia.active || ia.active[i] != 0;
+}
 
 ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ItemArgs ia;
@@ -72,6 +77,7 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.mass_flag = w.mass_flag.as<int32_t>();
     ia.split_tab = w.split_tab.as<float4>();
     ia.acc = nullptr;
+    ia.active = w.active;
     ia.chunk = w.chunk;       // the effective chunk the items were cut with
     return ia;
 }
@@ -361,7 +367,7 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     }
     if (ia.acc && ia.ioff[b + 1] - ia.ioff[b] == 1) {
         // the block's only item: finish here, with the reduction's arithmetic
-        if (lane < nt) {
+        if (lane < nt && target_on(ia, ia.perm[t])) {
             const int64_t i = ia.perm[t];
             const double sc = X.scale * (double)mu;
             ia.acc[i] = (float)(((double)ax - (double)cx) * sc);
@@ -393,6 +399,7 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
     __shared__ float4 tile[kBlock];
     const int64_t b = blockIdx.x;
     if (b >= nblock) return;
+    if (ia.ioff[b + 1] == ia.ioff[b]) return;        // a block without active targets
     const int lane = threadIdx.x;
     const int xbox = ia.bboxid[b];
     const BoxDev& X = ia.box[xbox];
@@ -449,7 +456,7 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
         wave_sync();
     }
     if (taken == 0) return;
-    if (lane < nt) {
+    if (lane < nt && target_on(ia, ia.perm[t])) {
         const int64_t i = ia.perm[t];
         ia.acc[i] += (float)(((double)ax - (double)cx) * X.scale);
         ia.acc[N + i] += (float)(((double)ay - (double)cy) * X.scale);
@@ -531,7 +538,7 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
         const int64_t b = g / kBlock;
         const int l = (int)(g % kBlock);
         if (l >= ia.bcount[b]) continue;
-        if (ia.ioff[b + 1] - ia.ioff[b] == 1) continue;     // written by the PP kernel
+        if (ia.ioff[b + 1] - ia.ioff[b] <= 1) continue;     // written by the PP kernel, or skipped
         double sx = 0, sy = 0, sz = 0;
         const int64_t end = ia.ioff[b + 1];
         int64_t it = ia.ioff[b];
@@ -560,6 +567,7 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
         }
         const double scale = ia.box[ia.bboxid[b]].scale;
         const int64_t i = perm[(int64_t)ia.bstart[b] + l];
+        if (!target_on(ia, i)) continue;
         acc[i] = (float)(sx * scale);
         acc[N + i] = (float)(sy * scale);
         acc[2 * N + i] = (float)(sz * scale);

@@ -800,12 +800,26 @@ __global__ void total_sources_kernel(const int64_t* __restrict__ soff_e, int64_t
     if (blockIdx.x == 0 && threadIdx.x == 0) *out = soff_e[F];
 }
 
+// Work items per block: its list in chunks (at least one item, so that every
+// target is written); none for a block without an active target when flags
+// are given.
 __global__ void item_count_kernel(const int32_t* __restrict__ slen,
                                   const int32_t* __restrict__ bcount, int64_t nblock, int chunk,
+                                  const uint8_t* __restrict__ active,
+                                  const int32_t* __restrict__ perm,
+                                  const int32_t* __restrict__ bstart,
                                   int32_t* __restrict__ icount,
                                   unsigned long long* __restrict__ cand) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblock) return;
+    if (active) {
+        bool on = false;
+        for (int32_t k = 0; k < bcount[b] && !on; ++k) on = active[perm[(int64_t)bstart[b] + k]] != 0;
+        if (!on) {
+            icount[b] = 0;
+            return;
+        }
+    }
     const int32_t s = slen[b];
     icount[b] = s <= 0 ? 1 : (s + chunk - 1) / chunk;
     // (target, listed source) pairs; the kernel prunes some sources further
@@ -993,7 +1007,7 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
 }
 
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
-                hipStream_t s, const MonoCfg& mcfg) {
+                hipStream_t s, const MonoCfg& mcfg, const uint8_t* active) {
     const int nbox = bd.nbox;
     const int64_t N = poff[nbox];
     w.nblock = w.nentry = w.nrange = w.nitem = w.candidates = 0;
@@ -1128,9 +1142,10 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     if (chunk64 > INT32_MAX / 2) chunk64 = INT32_MAX / 2;
     const int chunk = (int)chunk64;
     w.chunk = chunk;
+    w.active = active;
     hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(nb, 256)), dim3(256), 0, s,
-                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), nb, chunk,
-                       w.icount.as<int32_t>(), cand);
+                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), nb, chunk, active,
+                       w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>(), cand);
     PP_HIP(hipGetLastError());
     PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), nb, w.scan_ws, s));
     int64_t hostv[2];

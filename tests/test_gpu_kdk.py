@@ -49,6 +49,7 @@ def test_kdk_matches_oracle_integration(pp):
     po, vo = pos0.copy(), vel0.copy()
     ao = force(po)
     evals = 1
+    targets = n                                    # pp_kdk_init evaluates every target
     for step in range(2):
         a_gpu = K.accel().cpu().numpy().astype(np.float64)
         a_tot = a_gpu[:3] + a_gpu[3:]
@@ -62,6 +63,10 @@ def test_kdk_matches_oracle_integration(pp):
         info = K.info()
         assert info["deepest_level"] == lev.max() and info["force_evaluations"] == evals
         assert sum(info["level_count"]) == n
+        # short-range forces only for the particles whose step ends: particle
+        # i gets 2^level_i of them per top step
+        targets += int((2 ** lev).sum())
+        assert info["short_range_targets"] == targets < n * evals
     assert len(set(lev.tolist())) >= 2              # the test exercises several levels
     pg, vg = P.cpu().numpy(), V.cpu().numpy()
     dp = pg - po
