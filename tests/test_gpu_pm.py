@@ -108,3 +108,23 @@ def test_pm_plus_pp_is_newtonian_on_gpu(pp):
         a_ew = ewald_pair(pos[:, 0], pos[:, 1], L, 1.0, 1.0, 1.0 / (2 * p.rs))
         err = np.linalg.norm(a_pm + a_pp - a_ew) / np.linalg.norm(a_ew)
         assert err < tol, (sep, err)
+
+
+def test_pm_is_deterministic_and_reuses_plan_across_sizes(pp):
+    """The assignment has no atomics: repeated calls give identical bits;
+    a plan serves calls of different particle counts (its sort buffers
+    grow), each matching the oracle."""
+    rng = np.random.default_rng(8)
+    L, nm = 50.0, 32
+    p = BoxParams.from_mesh(L, nm)
+    plan = pp.PMPlan(p, nm)
+    for n in (5000, 300, 20000):
+        pos = W.mixture(rng, n, L, 0.7, 5)
+        mass = rng.uniform(0.5, 1.5, n).astype(np.float32) / n
+        P, M = dev(pos, torch.float64), dev(mass, torch.float32)
+        a1 = plan.accel(P, M).cpu().numpy()
+        a2 = plan.accel(P, M).cpu().numpy()
+        assert np.array_equal(a1, a2), n
+        from oracle import pm as opm
+        e = rel_errors(a1, opm.pm_accel(pos, mass.astype(np.float64), p, nm))
+        assert np.median(e) <= 1e-6 and e.max() <= 1e-4, (n, np.median(e), e.max())
