@@ -294,12 +294,15 @@ int pp_batch_autotune(pp_batch_plan* bp, const double* pos, const float* mass,
  * FFT; -grad phi by a 4-point central difference; linear (CIC)
  * interpolation to the particles.  Mesh arithmetic is FP64 (the FFTs by
  * hipFFT); the output is FP32.  pp_accel + pp_pm_accel is the whole force.
- * The mass assignment adds with FP64 atomics, so repeated calls can differ
- * in the last FP64 bits before the FP32 rounding.
+ * The mass assignment uses no atomics (the particles are sorted by mesh
+ * cell and every mesh point sums in a fixed order), so repeated calls on the
+ * same input give identical bits.
  *
  * pp_pm_plan_create: p gives L, rs (the filter scale) and G (rcut, eps,
  *   leaf_max and key_bits are validated but unused); 4 <= n_mesh <= 2048.
- *   The plan owns its meshes (about 56 n_mesh^3 bytes) and FFT plans.
+ *   The plan owns its meshes (about 80 n_mesh^3 bytes), FFT plans, and
+ *   per-particle sort buffers (about 90 bytes per particle plus up to
+ *   64 bytes per occupied cell) that grow on the first call with a larger n.
  * pp_pm_accel: pos SoA FP64 [3][n] (any real values, wrapped into [0, L)),
  *   mass FP32 [n], acc FP32 [3][n] written (not added); device pointers,
  *   enqueued on the stream.  Non-finite positions are placed at the origin
