@@ -178,6 +178,68 @@ def batched_error(boxes, acc_batched, per_box_targets=256, every=8):
             "max": float(e.max()) if e.size else 0.0}
 
 
+def bench_monopole_relative(plan, pos, mass, acc_exact, exact_step_ms, alpha=0.005, steps=5):
+    """Monopole acceptance with Gadget-2's relative criterion (alpha, the
+    exact FP32 accelerations as reference) on the same box: whole-step time
+    against the exact path, and the error against the exact result."""
+    import numpy as np
+    import torch
+    plan.set_monopole_relative(alpha, acc_exact)
+    acc = torch.empty_like(acc_exact)
+    plan.accel(pos, mass, out=acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.accel(pos, mass, out=acc)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = plan.stats()
+    a = acc.cpu().numpy().astype(np.float64)
+    r = acc_exact.cpu().numpy().astype(np.float64)
+    mag = np.linalg.norm(r, axis=0)
+    e = np.linalg.norm(a - r, axis=0)[mag > 0] / mag[mag > 0]
+    plan.set_monopole_relative(0.0)
+    return {"alpha": alpha, "ms_per_step": ms, "exact_ms_per_step": exact_step_ms,
+            "speedup": exact_step_ms / ms, "monopole_pairs": int(st["monopoles"]),
+            "lane_pairs": int(st["lane_pairs"]) if st["lane_pairs"] >= 0 else None,
+            "error_vs_exact": {"particles": int(e.size), "median": nearest_rank(e, 50),
+                               "p999": nearest_rank(e, 99.9), "max": float(e.max())}}
+
+
+def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, steps=2):
+    """Adaptive block-step KDK over the whole force (PP + PM) on the same box:
+    the top step is twice the median particle's step criterion, so the
+    particles spread over several levels; sub-steps evaluate the short-range
+    force for the particles whose step ends only."""
+    import numpy as np
+    import torch
+    import paper_1802_09824_amd as pp
+    amag = np.linalg.norm(acc_exact.cpu().numpy().astype(np.float64), axis=0)
+    dt = 2.0 * math.sqrt(2.0 * eta * box.params.eps / float(np.median(amag)))
+    P = pos.clone()
+    rng = np.random.default_rng(3)
+    V = torch.tensor(rng.normal(scale=1e-3, size=(3, box.n)), device="cuda")
+    K = pp.KDK(box.params, box.n, n_mesh=n_mesh, eta=eta, max_level=max_level)
+    K.init(P, mass)
+    K.step(P, V, mass, dt)
+    torch.cuda.synchronize()
+    i0 = K.info()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        K.step(P, V, mass, dt)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    i1 = K.info()
+    evals = (i1["force_evaluations"] - i0["force_evaluations"]) / steps
+    targets = (i1["short_range_targets"] - i0["short_range_targets"]) / steps
+    del K
+    return {"n_mesh": n_mesh, "eta": eta, "dt": dt, "ms_per_top_step": 1e3 * sec,
+            "force_evaluations_per_top_step": evals,
+            "short_range_targets_per_top_step": targets,
+            "fraction_of_full_short_range": targets / (evals * box.n),
+            "level_count": i1["level_count"][:max_level + 1]}
+
+
 def bench_pm(box, pos, mass, n_mesh, steps, with_error=True):
     """The long-range PM force of the same box (pp_pm_accel): CIC, FFTs,
     Green function with the Gaussian filter, gradient, interpolation.
@@ -375,6 +437,9 @@ def main():
         plan.set_tuning(variant=0)
     out["pm_long_range"] = bench_pm(box, pos, mass, 128, max(3, min(args.steps, 10)),
                                     with_error=not args.no_cpu_baseline)
+    plan.accel(pos, mass, out=acc)          # the exact FP32 result as reference
+    out["monopole_relative"] = bench_monopole_relative(plan, pos, mass, acc, ms_step)
+    out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
     if not args.no_batched:
         del plan, pos, mass, acc
         torch.cuda.empty_cache()
