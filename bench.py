@@ -42,9 +42,9 @@ TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "f3af06fb6689f2d23942ab5871db561185a2dccf",
-    "fetch_bytes": 360661956,     # FETCH_SIZE 176110.1 KiB x 1.9999
-    "write_bytes": 116572352,     # WRITE_SIZE 113840.2 KiB x 1.0000
+    "sha1": "513c874e0371d6ed73108f2a2c86ae7c83fa1269",
+    "fetch_bytes": 357826172,     # FETCH_SIZE 174725.3 KiB x 1.9999
+    "write_bytes": 116570240,     # WRITE_SIZE 113838.1 KiB x 1.0000
     "fetch_scale": 1.9999,           # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
     "write_scale": 1.0000,           # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
 }
@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-box batched-vs-per-box comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the monopole and adaptive-KDK legs (for profiling runs)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-box batched-vs-per-box comparison (for profiling)")
     ap.add_argument("--print-sources-sha1", action="store_true",
@@ -437,9 +439,10 @@ def main():
         plan.set_tuning(variant=0)
     out["pm_long_range"] = bench_pm(box, pos, mass, 128, max(3, min(args.steps, 10)),
                                     with_error=not args.no_cpu_baseline)
-    plan.accel(pos, mass, out=acc)          # the exact FP32 result as reference
-    out["monopole_relative"] = bench_monopole_relative(plan, pos, mass, acc, ms_step)
-    out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
+    if not args.no_extras:
+        plan.accel(pos, mass, out=acc)      # the exact FP32 result as reference
+        out["monopole_relative"] = bench_monopole_relative(plan, pos, mass, acc, ms_step)
+        out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
     if not args.no_batched:
         del plan, pos, mass, acc
         torch.cuda.empty_cache()
