@@ -259,6 +259,48 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         yi = (float)((pos_s[N + t] - (LOCAL ? oy : 0.0)) * inv_len);
         zi = (float)((pos_s[2 * N + t] - (LOCAL ? oz : 0.0)) * inv_len);
     }
+    // Four boxes around the FP32 offsets of the four runs of 16 consecutive
+    // targets (key order), kept in LDS: a source is staged when it comes
+    // within the cut of any of them, which drops about 5 % of the sources
+    // that pass the whole block's box.  Widened like the block box.
+    constexpr int GROUPS = 4;
+    constexpr int GW = kBlock / GROUPS;
+    __shared__ float4 qb[2 * GROUPS];
+    if (LOCAL) {
+        float ax_ = lane < nt ? xi : INFINITY, bx_ = lane < nt ? xi : -INFINITY;
+        float ay_ = lane < nt ? yi : INFINITY, by_ = lane < nt ? yi : -INFINITY;
+        float az_ = lane < nt ? zi : INFINITY, bz_ = lane < nt ? zi : -INFINITY;
+#pragma unroll
+        for (int m = 1; m < GW; m <<= 1) {
+            ax_ = fminf(ax_, __shfl_xor(ax_, m));
+            bx_ = fmaxf(bx_, __shfl_xor(bx_, m));
+            ay_ = fminf(ay_, __shfl_xor(ay_, m));
+            by_ = fmaxf(by_, __shfl_xor(by_, m));
+            az_ = fminf(az_, __shfl_xor(az_, m));
+            bz_ = fmaxf(bz_, __shfl_xor(bz_, m));
+        }
+        // an empty group repeats group 0
+        {
+            const bool empty = lane >= nt;
+            const float r0 = readlane_f(ax_, 0), r1 = readlane_f(bx_, 0), r2 = readlane_f(ay_, 0);
+            const float r3 = readlane_f(by_, 0), r4 = readlane_f(az_, 0), r5 = readlane_f(bz_, 0);
+            ax_ = empty ? r0 : ax_;
+            bx_ = empty ? r1 : bx_;
+            ay_ = empty ? r2 : ay_;
+            by_ = empty ? r3 : by_;
+            az_ = empty ? r4 : az_;
+            bz_ = empty ? r5 : bz_;
+        }
+        wave_sync();
+        if (lane % GW == 0) {
+            const int g = lane / GW;
+            qb[2 * g] = make_float4(0.5f * (ax_ + bx_), 0.5f * (ay_ + by_), 0.5f * (az_ + bz_),
+                                    0.5f * (bx_ - ax_) * 1.0001f + 1e-6f);
+            qb[2 * g + 1] = make_float4(0.5f * (by_ - ay_) * 1.0001f + 1e-6f,
+                                        0.5f * (bz_ - az_) * 1.0001f + 1e-6f, 0.f, 0.f);
+        }
+        wave_sync();
+    }
     const int64_t r_lo = ia.roff[b], r_hi = ia.roff[b + 1] - 1;
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     int count = 0;                                   // staged sources (wave-uniform)
@@ -301,10 +343,21 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             v.y = (float)((py + sy - oy) * inv_len);
             v.z = (float)((pz + sz - oz) * inv_len);
             v.w = equal ? P.cut2 : pm;
-            const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
-            const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
-            const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
-            keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+            if (LOCAL) {
+#pragma unroll
+                for (int g = 0; g < GROUPS; ++g) {
+                    const float4 c = qb[2 * g], h = qb[2 * g + 1];
+                    const float gx = fmaxf(fabsf(v.x - c.x) - c.w, 0.f);
+                    const float gy = fmaxf(fabsf(v.y - c.y) - h.x, 0.f);
+                    const float gz = fmaxf(fabsf(v.z - c.z) - h.y, 0.f);
+                    keep = keep || fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+                }
+            } else {
+                const float gx = fmaxf(fabsf(v.x) - hx, 0.f);
+                const float gy = fmaxf(fabsf(v.y) - hy, 0.f);
+                const float gz = fmaxf(fabsf(v.z) - hz, 0.f);
+                keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < keep2;
+            }
             if (!LOCAL) {
                 v.x = (float)((px + sx) * inv_len);
                 v.y = (float)((py + sy) * inv_len);
