@@ -42,9 +42,9 @@ TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "513c874e0371d6ed73108f2a2c86ae7c83fa1269",
-    "fetch_bytes": 357826172,     # FETCH_SIZE 174725.3 KiB x 1.9999
-    "write_bytes": 116570240,     # WRITE_SIZE 113838.1 KiB x 1.0000
+    "sha1": "ce2d28cfec7294619ccc82e19c888f68921a0833",
+    "fetch_bytes": 367515959,     # FETCH_SIZE 179456.9 KiB x 1.9999
+    "write_bytes": 116576000,     # WRITE_SIZE 113843.8 KiB x 1.0000
     "fetch_scale": 1.9999,           # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
     "write_scale": 1.0000,           # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
 }
