@@ -189,6 +189,14 @@ EDGE_CASES = {
     "lattice": lambda: (W.lattice(8, 8.0), BoxParams(L=8.0, rs=0.6, rcut=2.7, eps=0.02)),
     "leaf1": lambda: (np.random.default_rng(4).random((3, 1000)) * 20, BoxParams(L=20.0, rs=1.0, rcut=4.5, eps=0.01, leaf_max=1)),
     "leaf1024": lambda: (small_clustered(5000, 30.0, 0.6, 4, 8), BoxParams(L=30.0, rs=1.0, rcut=4.5, eps=0.01, leaf_max=1024)),
+    # a 16^3 key grid: clustered cells hold more than leaf_max particles, so
+    # leaves at the finest level exceed leaf_max
+    "bits4": lambda: (small_clustered(3000, 30.0, 0.7, 3, 9), BoxParams(L=30.0, rs=1.0, rcut=4.5, eps=0.01, key_bits=4)),
+    # a cut well inside the split scale (the polynomial's variable stays near 0)
+    "short-cut": lambda: (np.random.default_rng(5).random((3, 3000)) * 20, BoxParams(L=20.0, rs=1.0, rcut=1.5, eps=0.01)),
+    # lengths and G far from 1: the kernel's length unit follows r_s
+    "large-units": lambda: (np.random.default_rng(6).random((3, 2000)) * 2e4, BoxParams(L=2e4, rs=1e3, rcut=4.5e3, eps=10.0, G=6.674e-11)),
+    "small-units": lambda: (small_clustered(2500, 2e-3, 0.5, 3, 10), BoxParams(L=2e-3, rs=1e-4, rcut=4.5e-4, eps=2e-6, G=3.0e4)),
 }
 
 
