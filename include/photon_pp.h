@@ -300,10 +300,11 @@ int pp_batch_autotune(pp_batch_plan* bp, const double* pos, const float* mass,
  *
  * pp_pm_plan_create: p gives L, rs (the filter scale) and G (rcut, eps,
  *   leaf_max and key_bits are validated but unused); 4 <= n_mesh <= 2048.
- *   The plan owns its meshes (about 80 n_mesh^3 bytes), FFT plans, and
+ *   The plan owns its meshes (about 60 n_mesh^3 bytes), FFT plans, and
  *   per-particle sort buffers (about 90 bytes per particle plus up to
  *   64 bytes per occupied cell) that grow on the first call with a larger n.
- * pp_pm_accel: pos SoA FP64 [3][n] (any real values, wrapped into [0, L)),
+ * pp_pm_accel: n < 2^31 particles; pos SoA FP64 [3][n] (any real values,
+ *   wrapped into [0, L)),
  *   mass FP32 [n], acc FP32 [3][n] written (not added); device pointers,
  *   enqueued on the stream.  Non-finite positions are placed at the origin
  *   (they are not detected here; pp_accel reports them). */
