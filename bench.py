@@ -413,6 +413,8 @@ def main():
         "interactions_per_step": interactions,
         "candidates_per_step": int(st["candidates"]),
         "evaluated_pairs_per_step": int(st["evaluated"]),
+        "pp_kernel_evaluated_pairs_per_s": int(st["evaluated"]) / (k_ms * 1e-3),
+        "useful_fraction": interactions / max(int(st["evaluated"]), 1),
         "pp_kernel_interactions_per_s": interactions / (k_ms * 1e-3),
         "pct_fp32_peak_paper_22flop": 100.0 * interactions * PAPER_FLOPS_PER_INTERACTION
         / (k_ms * 1e-3) / FP32_VECTOR_PEAK,
