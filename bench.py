@@ -242,6 +242,31 @@ def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, ste
             "level_count": i1["level_count"][:max_level + 1]}
 
 
+def bench_small_box(steps=20):
+    """The 32,768-particle uniform box (L = 100): a launch-latency case, one
+    whole pp_accel step per call."""
+    import torch
+    import workloads
+    import paper_1802_09824_amd as pp
+    b = workloads.make_config(1)
+    pos = torch.tensor(b.pos, device="cuda")
+    mass = torch.tensor(b.mass, device="cuda")
+    plan = pp.Plan(b.params, b.n)
+    acc = plan.accel(pos, mass)
+    inter = plan.count_interactions()
+    for _ in range(3):
+        plan.accel(pos, mass, out=acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.accel(pos, mass, out=acc)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    del plan
+    return {"workload": b.name, "n": b.n, "interactions_per_step": inter, "ms_per_step": 1e3 * sec,
+            "interactions_per_s": inter / sec}
+
+
 def bench_pm(box, pos, mass, n_mesh, steps, with_error=True):
     """The long-range PM force of the same box (pp_pm_accel): CIC, FFTs,
     Green function with the Gaussian filter, gradient, interpolation.
@@ -445,6 +470,7 @@ def main():
         plan.accel(pos, mass, out=acc)      # the exact FP32 result as reference
         out["monopole_relative"] = bench_monopole_relative(plan, pos, mass, acc, ms_step)
         out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
+        out["small_box"] = bench_small_box()
     if not args.no_batched:
         del plan, pos, mass, acc
         torch.cuda.empty_cache()
