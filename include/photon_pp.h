@@ -231,8 +231,9 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *               table in LDS (128 quadratic pieces, the form sec. 3.1
  *               describes) instead of the polynomial.  0 is the production
  *               kernel.
- *  groups       reserved, must be 1 (sources are pruned against the
- *               target block's bounding box).
+ *  groups       reserved, must be 1 (every lane of a wave sweeps every
+ *               staged source; sources are pruned against four boxes around
+ *               the block's runs of 16 targets before they are staged).
  * The chunk grows by itself when the lists are long enough that more than
  * 2^21 work items would be needed.
  * Defaults: plans {2048, 1, 20, 0, 0, 1}; batch plans {2048, 1, 20, 1, 0, 1}. */
@@ -244,10 +245,10 @@ int pp_plan_set_tuning(pp_plan* plan, const pp_tuning* t);
 
 /* Autotuner: times the PP stage (HIP events, median of 3 after a warm run)
  * for every chunk in {1024, 2048, 4096, 8192} and launch shape in {one
- * workgroup per item, persistent with 8, 16 or 32 waves per CU} on the
+ * workgroup per item, persistent with 12, 20 or 24 waves per CU} on the
  * given particles, and keeps the fastest in the plan.  With cache_path
  * (may be NULL) the choice is looked up first and stored afterwards, one
- * line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent waves graph" per shape
+ * line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent waves graph groups" per shape
  * class.  The caller's inputs are not modified.  Synchronises the stream.  */
 int pp_autotune(pp_plan* plan, const double* pos, const float* mass, int64_t n,
                 const char* cache_path, void* stream);
