@@ -42,7 +42,7 @@ TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "ce2d28cfec7294619ccc82e19c888f68921a0833",
+    "sha1": "51d5883524584880335d2139c8d056ca875a8f95",
     "fetch_bytes": 367515959,     # FETCH_SIZE 179456.9 KiB x 1.9999
     "write_bytes": 116576000,     # WRITE_SIZE 113843.8 KiB x 1.0000
     "fetch_scale": 1.9999,           # 1 GiB copy: 1048576 KiB / FETCH_SIZE read

@@ -215,9 +215,10 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 // the mass; the loads of the next window are issued before the current tile
 // is swept.  A fetched source is shifted by its periodic image, made
 // relative to the FP64 block centre, scaled by 1/ell and rounded to FP32,
-// and dropped if it lies at r_cut or more from the block's box.  Survivors
-// are compacted with a ballot into a 128-entry LDS ring; every 64 survivors
-// are swept by all lanes with broadcast LDS reads.
+// and dropped if it lies at r_cut or more from each of the four boxes
+// around the block's runs of 16 targets.  Survivors are compacted with a
+// ballot into a 128-entry LDS ring; every 64 survivors are swept by all
+// lanes with broadcast LDS reads.
 template <int VAR>
 __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
                                         const double* __restrict__ pos_s,
