@@ -112,3 +112,40 @@ def test_kdk_argument_checks(pp):
     x = torch.rand((3, 10), dtype=torch.float64, device="cuda") * 10
     with pytest.raises(pp.PPError):            # init first
         K.step(x, torch.zeros_like(x), torch.ones(10, dtype=torch.float32, device="cuda"), 0.1)
+
+
+def test_kdk_short_range_only_matches_oracle(pp):
+    """n_mesh = 0: the driver integrates the short-range force alone; the
+    sub-steps evaluate it for the particles whose step ends only."""
+    import oracle
+    from oracle import kdk as okdk
+    rng = np.random.default_rng(21)
+    L = 30.0
+    p = BoxParams.from_mesh(L, 24)
+    n = 2000
+    pos0 = W.mixture(rng, n, L, 0.6, 5)
+    vel0 = rng.normal(scale=0.05, size=(3, n))
+    mass = np.full(n, 1.0 / n, dtype=np.float32)
+    eta, dt, kmax = 0.02, 3.0, 3
+    m64 = mass.astype(np.float64)
+
+    def force(x):
+        return oracle.accel(x, m64, p)["acc"]
+
+    K = pp.KDK(p, n, n_mesh=0, eta=eta, max_level=kmax)
+    P, V, M = dev(pos0, torch.float64), dev(vel0, torch.float64), dev(mass, torch.float32)
+    K.init(P, M)
+    K.step(P, V, M, dt)
+    lev = K.levels().cpu().numpy().astype(np.int64)
+    assert len(set(lev.tolist())) >= 2
+    po, vo, _, ev = okdk.kdk_top_step(pos0, vel0, force(pos0), force, dt, lev, L)
+    info = K.info()
+    assert info["force_evaluations"] == 1 + ev
+    assert info["short_range_targets"] == n + int((2 ** lev).sum())
+    pg, vg = P.cpu().numpy(), V.cpu().numpy()
+    dp = pg - po
+    dp -= L * np.round(dp / L)
+    disp = np.linalg.norm(((po - pos0 + L / 2) % L) - L / 2, axis=0)
+    assert np.median(np.linalg.norm(dp, axis=0)) <= 1e-5 * np.median(disp) + 1e-12
+    dv = np.linalg.norm(vg - vo, axis=0) / np.maximum(np.linalg.norm(vo, axis=0), 1e-12)
+    assert np.median(dv) <= 1e-5
