@@ -288,6 +288,8 @@ class Plan:
         """Gadget-2's relative opening test for accel against reference
         accelerations acc_ref [3][n] (FP32, device); alpha = 0 turns it off."""
         if alpha > 0:
+            if acc_ref is None:
+                raise ValueError("alpha > 0 needs the reference accelerations acc_ref")
             n = acc_ref.shape[1]
             ptr = _dev(acc_ref, torch.float32, (3, n), "acc_ref")
         else:
