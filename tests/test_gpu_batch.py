@@ -179,3 +179,25 @@ def test_equal_mass_boxes_mixed_with_unequal(pp, oracle_mod):
     rel = np.linalg.norm(a - c, axis=0) / np.where(mag > 0, mag, 1)
     assert np.median(rel) <= 1e-6 and rel.max() <= 1e-4
     assert np.array_equal(acc[:, boxes[0].n:], acc2[:, boxes[0].n:])
+
+
+def test_full_64_box_batch_sampled(pp, oracle_mod):
+    """The benchmark's batch (64 boxes, about 32 M particles) in the launch
+    configuration it is timed in (persistent kernel replayed from a graph),
+    on 256 seeded targets of every 8th box against the FP64 oracle."""
+    boxes = W.make_batch()
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    assert bp.get_tuning()["use_graph"] == 1 and bp.get_tuning()["persistent"] == 1
+    P, M = dev(pos, torch.float64), dev(mass, torch.float32)
+    bp.accel(P, M)
+    acc = bp.accel(P, M).cpu().numpy()                 # a graph replay
+    rng = np.random.default_rng(1803)
+    off = np.cumsum([0] + [b.n for b in boxes])
+    for k in range(0, len(boxes), 8):
+        b = boxes[k]
+        t = np.sort(rng.choice(b.n, min(b.n, 256), replace=False))
+        ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, targets=t, pair_abs=True)
+        s = parity.summary(acc[:, off[k] + t], ref)
+        assert s["zero_ok"] and s["median"] <= 1e-6 and s["p999"] <= 1e-4, (b.name, s)
+        assert s["robust_max"] <= parity.ROBUST_MAX, (b.name, s)
