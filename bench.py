@@ -103,6 +103,14 @@ def nearest_rank(x, q):
     return float(x[max(1, int(math.ceil(q / 100.0 * x.size))) - 1])
 
 
+def host_cores():
+    """Cores this process may run on (what `nproc` prints)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
 def cpu_baseline(box, acc_gpu, budget_s):
     """Time the FP64 oracle on a seeded sample of targets; compare the GPU
     accelerations of the same targets."""
@@ -120,10 +128,13 @@ def cpu_baseline(box, acc_gpu, budget_s):
     ref = oracle.accel(box.pos, mass64, box.params, targets=targets)
     sec = time.perf_counter() - t0
     inter = int(ref["n_inter"].sum())
-    base = {"value": inter / sec, "unit": "interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    checks = k * (box.n - 1)
+    base = {"value": inter / sec, "unit": "interactions/s", "cores": host_cores(),
+            "threads": oracle.num_threads(), "kind": "oracle",
+            "pair_checks_per_s": checks / sec,
             "sample": f"{k} seeded random targets of the same box against all {box.n} sources "
-                      f"(FP64 direct sum, {inter} interactions, {sec:.1f} s)"}
+                      f"(FP64 direct sum over every source: {checks} pair distance checks, "
+                      f"{inter} of them within the cut, {sec:.1f} s)"}
     errs = sample_errors(acc_gpu, targets, ref)
     # condition-robust error |a - a*| / sum_j |a_ij| on every 8th sampled
     # target (a second, untimed oracle call that also sums the pair magnitudes)

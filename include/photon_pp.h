@@ -184,7 +184,7 @@ typedef struct pp_stats {
                                monopole acceptance on (0 when off, -1 if unknown) */
 } pp_stats;
 /* Waits for the last PP kernel when timing is on.                          */
-/* Monopole acceptance (sec. 3.4, the 1-to-N case of the dual tree walk) for
+/* Monopole acceptance (sec. 3.3, the 1-to-N case of the dual tree walk) for
  * pp_accel on this plan: a source tree node of 64 leaves or more whose box
  * satisfies (A + B) / R <= theta against the target block (A, B the longest
  * box sides, R the distance of the box centres; this implies

@@ -133,6 +133,10 @@ struct Batch {
     uint64_t graph_gen = 0;
     const void* graph_acc = nullptr;
     const void* graph_active = nullptr;
+    // kernel arguments passed by value: the chunk the items were cut with and
+    // the row stride of the SoA particle arrays
+    int graph_chunk = 0;
+    int64_t graph_n = -1;
 
     ~Batch() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -285,6 +289,8 @@ struct Batch {
         graph_gen = alloc_generation();
         graph_acc = acc;
         graph_active = w.active;
+        graph_chunk = w.chunk;
+        graph_n = w.pos_n;
         graph_variant = graph_key();
         return PP_OK;
     }
@@ -298,7 +304,8 @@ struct Batch {
         PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.nitem + 1)));
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
-                graph_active != w.active || graph_variant != graph_key())
+                graph_active != w.active || graph_variant != graph_key() ||
+                graph_chunk != w.chunk || graph_n != w.pos_n)
                 PP_TRY(capture(acc));
             if (timing) PP_HIP(hipEventRecord(ev0, s));
             PP_HIP(hipGraphLaunch(gexec, s));

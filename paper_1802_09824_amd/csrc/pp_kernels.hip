@@ -437,7 +437,7 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     o[2 * kBlock + lane] = (float)(((double)az - (double)cz) * (double)mu);
 }
 
-// Monopoles (sec. 3.4, 1 to N): one wave per target block walks the block's
+// Monopoles (sec. 3.3, 1 to N): one wave per target block walks the block's
 // entries of the list expansion; accepted nodes become sources of their
 // mass at their centre of mass (FP64 sums, shifted by their periodic
 // image, relative to the FP64 block centre, in units of ell) and go through

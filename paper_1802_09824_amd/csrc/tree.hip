@@ -296,7 +296,7 @@ __device__ __forceinline__ int64_t gap2_min(const IBox& A, const IBox& B, const 
 }
 
 // Monopole acceptance of the node of box B (global index g) for target box
-// A (block b) under shift s (sec. 3.4), every enabled test required:
+// A (block b) under shift s (sec. 3.3), every enabled test required:
 //  * geometric: (A + B) / R <= theta with A, B the longest box sides and R
 //    the distance of the box centres, tested as (2 (A + B))^2 <= theta^2
 //    (2R)^2 from integer half-cell coordinates (for theta < 1 this gives

@@ -99,6 +99,49 @@ def test_graph_replays_repeat_eager(pp):
         assert torch.isfinite(junk)
 
 
+def test_graph_recaptured_after_chunk_change(pp):
+    """The chunk the work items are cut with is a kernel argument baked into
+    the captured graph: after set_tuning(chunk=...) the replay must give what
+    the same chunk gives without a graph, bit for bit."""
+    boxes = small_batch(6, seed=31)
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    p, m = dev(pos, torch.float64), dev(mass, torch.float32)
+    assert bp.get_tuning()["use_graph"] == 1
+    bp.accel(p, m)
+    bp.accel(p, m)                                   # a replay at the default chunk
+    bp.set_tuning(chunk=128)
+    got = bp.accel(p, m).cpu().numpy()
+    got2 = bp.accel(p, m).cpu().numpy()
+    bp.set_tuning(use_graph=0)
+    ref = bp.accel(p, m).cpu().numpy()
+    assert bp.stats()["nitem"] > bp.stats()["nblock"]   # the small chunk splits lists
+    assert np.array_equal(got, ref) and np.array_equal(got2, ref)
+
+
+def test_graph_recaptured_after_smaller_n(pp):
+    """The particle count (the row stride of the SoA arrays) is a kernel
+    argument too: a plan replaying its graph at n and then at n/2 must give
+    the non-graph results, and write nothing past 3 (n/2) floats."""
+    b = W.make_config(1)
+    n2 = b.n // 2
+    plan = pp.Plan(b.params, b.n)
+    plan.set_tuning(persistent=1, use_graph=1)
+    ref_plan = pp.Plan(b.params, b.n)
+    p, m = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
+    full = plan.accel(p, m).cpu().numpy()
+    assert np.array_equal(full, ref_plan.accel(p, m).cpu().numpy())
+    p2, m2 = p[:, :n2].contiguous(), m[:n2].contiguous()
+    buf = torch.full((3 * b.n,), 7.0, dtype=torch.float32, device="cuda")
+    out = buf[:3 * n2].view(3, n2)
+    plan.accel(p2, m2, out=out)
+    half = out.cpu().numpy()
+    assert np.array_equal(half, ref_plan.accel(p2, m2).cpu().numpy())
+    assert torch.all(buf[3 * n2:] == 7.0)
+    again = plan.accel(p, m).cpu().numpy()
+    assert np.array_equal(again, full)
+
+
 @pytest.mark.parametrize("tuning", [dict(persistent=1, waves_per_cu=4), dict(chunk=256),
                                     dict(chunk=64, persistent=1, waves_per_cu=1),
                                     dict(persistent=1, use_graph=1, waves_per_cu=32)])
