@@ -1,205 +1,245 @@
-"""FP64 CPU oracle for the short-range force with monopole acceptance.
+"""FP64 CPU oracle: the short-range force by the dual tree traversal of
+sec. 3.3, with monopole (1-to-N) acceptance.
 
 TEST INFRASTRUCTURE ONLY: only the tests may import this module.  It shares
-no code with the HIP library and never imports it.
+no code with the HIP library and never imports it.  It builds its own tree
+from the oracle's keys, sort order and cells (oracle/__init__.py); the
+library's blocks, node groups and operation order appear nowhere here.
 
-The dual-tree walk of sec. 3.4 (Dual Tree Traversal) with monopoles
-(sec. 3.1, after Gadget-2), restated on the structures of this build, in
-the algorithm's order:
+Tree (sec. 3.2): the oct-tree over the particles sorted along the
+Peano-Hilbert curve.  The node of level l that holds particle k is the set of
+particles whose keys share the top 3 l bits with k's key: a contiguous run
+of the sorted particles, occupying the aligned cube of side L / 2^l (in grid
+cells: side 2^(b - l), lower corner = any of its cells with the low b - l
+bits cleared).  A node is a leaf (sec. 3.3, "a package of a given number of
+particles") when it holds at most leaf_max particles or lies at the finest
+level; otherwise its children are its non-empty octants.  Every node carries
+its mass M (the sum of its particles' masses) and its centre of mass.
 
-* particles in Peano-Hilbert order (sec. 4.1) with the octree leaves of
-  sec. 3.2-3.3 (maximal nodes with at most leaf_max particles);
-* target nodes: runs of at most 64 consecutive particles, cut where their
-  integer box would grow wider than 2 r_cut (kept whole: the paper's MIC
-  choice preserves the target node and opens the other one);
-* source nodes: the hierarchy over the leaves in which a node of level h
-  groups 8 consecutive nodes of level h - 1 (contiguous in memory, as
-  sec. 3.2 requires of tree nodes); each node has its integer bounding box,
-  its mass and its centre of mass;
-* per target node A and periodic image s, walk the source tree from the
-  root: a node whose box lies at r_cut or more from A's box is skipped; a
-  node of level >= 2 is taken as a monopole when every enabled test holds:
-  the geometric one, (A + B) / R <= theta (A, B the longest box sides, R
-  the distance of the box centres; for theta < 1 this also gives
-  B / (R - A) <= theta), and Gadget-2's relative one of sec. 3.1,
-  G M B^2 / r^4 <= alpha |a| (M the node mass, r the gap between the two
-  boxes, |a| the smallest reference acceleration among A's targets); other
-  nodes are opened; leaves reached this way are summed particle by particle
-  (the N-to-M PP of sec. 3.3);
-* a monopole acts on every target of A as a particle of the node's mass at
-  its centre of mass: the same softened, split, cut pair force.
+Traversal (sec. 3.3), with the policy the paper takes on MIC: the target node
+is kept and the other node is opened.  Each target leaf A is walked against
+the source tree from the root, once per periodic image sigma of the sources
+(shift sigma L, sigma in {-1, 0, 1}^3):
+
+* a source node B whose shifted cube lies at r_cut or more from A's cube is
+  skipped: the short-range force vanishes there (sec. 3.1);
+* B is accepted when every enabled test holds:
+    - geometric (theta > 0): the two opening angles of sec. 3.3,
+        theta1 = (B + A) / R,   theta2 = B / (R - A),
+      are both at most theta (A, B the cube sides, R the distance between
+      the cube centres; theta2 counts as infinite when R <= A);
+    - relative (alpha > 0): Gadget-2's criterion that sec. 3.1 follows,
+        G M / s^2 (l / s)^2 <= alpha |a|,
+      holds for every target particle of A, with s the particle's distance
+      to B's centre of mass, l the side of B's cube and |a| the particle's
+      reference acceleration;
+  a node whose cube holds targets of A (A itself or one of its ancestors,
+  unshifted) is never accepted.  Then every target of A gains the force of
+  one particle of mass M at B's centre of mass (the 1-to-N case);
+* otherwise a leaf B is summed particle by particle with A (the N-to-M case,
+  the PP kernel of sec. 3.3), and any other B is opened.
+
+With both tests off nothing is accepted and the walk reaches every pair: the
+result is the plain short-range sum.  Every interaction, particle or
+monopole, uses the short-range pair force of the rest of the oracle:
+    a_i += G m_j d g(s_eps / 2 r_s) / s_eps^3,  d = x_j + sigma L - x_i,
+kept when the unsoftened distance s satisfies 0 < s < r_cut, with
+s_eps^2 = s^2 + eps^2 and g the factor of Eq. equ:split.
 """
 from __future__ import annotations
+
+import dataclasses
+import math
 
 import numpy as np
 from scipy.special import erfc
 
-from . import hilbert_keys, sort_order, leaves, leaf_boxes, quantise
+from . import hilbert_keys, sort_order, quantise
+
+SHIFTS = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
 
 
-def _split(x):
+def split_factor(x):
+    """g(x) = erfc(x) + (2 x / sqrt(pi)) exp(-x^2), x = s / (2 r_s): Eq. equ:split."""
     return erfc(x) + 2.0 * x / np.sqrt(np.pi) * np.exp(-x * x)
 
 
-def _blocks(q, n, emax):
-    """Target nodes: (start, count, lo[3], hi[3]) in key order."""
-    out = []
-    for k0 in range(0, n, 64):
-        k1 = min(k0 + 64, n)
-        qs = q[:, k0:k1].astype(np.int64)
-        lo, hi = qs.min(1), qs.max(1) + 1
-        if np.all(hi - lo <= emax):
-            out.append((k0, k1 - k0, lo, hi))
-            continue
-        start = k0
-        blo, bhi = qs[:, 0].copy(), qs[:, 0] + 1
-        for kk in range(k0 + 1, k1):
-            qq = qs[:, kk - k0]
-            ulo, uhi = np.minimum(blo, qq), np.maximum(bhi, qq + 1)
-            if np.any(uhi - ulo > emax):
-                out.append((start, kk - start, blo, bhi))
-                start, blo, bhi = kk, qq.copy(), qq + 1
-            else:
-                blo, bhi = ulo, uhi
-        out.append((start, k1 - start, blo, bhi))
-    return out
+@dataclasses.dataclass
+class Node:
+    level: int
+    begin: int          # particles [begin, end) in key order
+    end: int
+    lo: tuple           # lower cube corner, grid cells
+    side: int           # cube side, grid cells
+    flo: tuple          # lower cube corner, lengths
+    width: float        # cube side, length
+    centre: tuple       # cube centre, lengths
+    mass: float
+    com: np.ndarray     # centre of mass [3]
+    children: list
+    leaf: bool
 
 
-def _gap2(alo, ahi, blo, bhi, s, W):
-    sh = np.asarray(s, dtype=np.int64) * W
-    g = np.maximum(np.maximum(blo + sh - ahi, alo - bhi - sh), 0)
-    return int((g * g).sum())
+class Tree:
+    """The oct-tree of sec. 3.2 over one periodic box (key order)."""
+
+    def __init__(self, pos, mass, params):
+        p = params
+        self.params = p
+        self.L = float(p.L)
+        self.bits = int(p.key_bits)
+        self.cell = self.L / float(1 << self.bits)
+        pos = np.asarray(pos, dtype=np.float64)
+        self.n = pos.shape[1]
+        keys = hilbert_keys(pos, self.L, self.bits)
+        self.order = sort_order(keys)
+        self.keys = keys[self.order]
+        self.q = quantise(pos, self.L, self.bits)[:, self.order].astype(np.int64)
+        self.x = (pos - self.L * np.floor(pos / self.L))[:, self.order]
+        self.m = np.asarray(mass, dtype=np.float64)[self.order]
+        self.nodes: list[Node] = []
+        self.root = self._make(0, 0, self.n) if self.n > 0 else None
+
+    def _make(self, level, b0, e0):
+        b = self.bits
+        idx = len(self.nodes)
+        self.nodes.append(None)
+        side = 1 << (b - level)
+        lo = tuple(int((self.q[k, b0] >> (b - level)) << (b - level)) for k in range(3))
+        msum = float(self.m[b0:e0].sum())
+        com = (self.m[b0:e0] * self.x[:, b0:e0]).sum(axis=1) / msum if msum > 0 else \
+            self.x[:, b0:e0].mean(axis=1)
+        leaf = (e0 - b0) <= self.params.leaf_max or level == b
+        children = []
+        if not leaf:
+            digit = (self.keys[b0:e0] >> np.uint64(3 * (b - level - 1))) & np.uint64(7)
+            cuts = b0 + np.searchsorted(digit, np.arange(9, dtype=np.uint64))
+            for d in range(8):
+                if cuts[d + 1] > cuts[d]:
+                    children.append(self._make(level + 1, int(cuts[d]), int(cuts[d + 1])))
+        flo = tuple(c * self.cell for c in lo)
+        width = side * self.cell
+        centre = tuple(c + 0.5 * width for c in flo)
+        self.nodes[idx] = Node(level, b0, e0, lo, side, flo, width, centre, msum, com, children, leaf)
+        return idx
+
+    def leaves(self):
+        return [i for i, nd in enumerate(self.nodes) if nd.leaf]
+
+    def contains(self, outer, inner):
+        """Node `outer` is `inner` or one of its ancestors."""
+        o, i = self.nodes[outer], self.nodes[inner]
+        return o.level <= i.level and o.begin <= i.begin and i.end <= o.end
+
+    def cube_gap2(self, a, b, s):
+        """Squared distance between node a's cube and node b's cube shifted by s L."""
+        A, B = self.nodes[a], self.nodes[b]
+        d2 = 0.0
+        for k in range(3):
+            blo = B.flo[k] + s[k] * self.L
+            g = max(0.0, blo - (A.flo[k] + A.width), A.flo[k] - (blo + B.width))
+            d2 += g * g
+        return d2
 
 
-def _accept(alo, ahi, blo, bhi, s, W, theta, rel=None):
-    """The enabled acceptance tests, each squared so that it is a fixed
-    sequence of FP64 operations on integers and the given masses: the
-    geometric one as (2 (A + B))^2 <= theta^2 (2 R)^2 in half cells, the
-    relative one as (G M (B cell)^2)^2 <= alpha^2 |a|^2 (r cell)^8.
-    rel = (G, M, cell, alpha, |a|^2) or None."""
-    A = int((ahi - alo).max())
-    B = int((bhi - blo).max())
-    if theta > 0:
-        D = (blo + bhi + 2 * np.asarray(s, dtype=np.int64) * W) - (alo + ahi)
-        R2x4 = int((D * D).sum())
-        lhs = float(2 * (A + B)) ** 2
-        if not lhs <= (theta * theta) * float(R2x4):
-            return False
-    if rel is not None:
-        G, M, cell, alpha, a2 = rel
-        bc = float(B) * cell
-        lhs = ((G * M) * bc) * bc
-        g2 = (float(_gap2(alo, ahi, blo, bhi, s, W)) * cell) * cell
-        if not lhs * lhs <= ((alpha * alpha) * a2) * ((g2 * g2) * (g2 * g2)):
-            return False
-    return True
+def opening_angles(tree, a, b, s):
+    """(theta1, theta2) of sec. 3.3 for target node a and source node b shifted by s L."""
+    A, B = tree.nodes[a], tree.nodes[b]
+    L = tree.L
+    dx = B.centre[0] + s[0] * L - A.centre[0]
+    dy = B.centre[1] + s[1] * L - A.centre[1]
+    dz = B.centre[2] + s[2] * L - A.centre[2]
+    R = math.sqrt(dx * dx + dy * dy + dz * dz)
+    th1 = (B.width + A.width) / R if R > 0 else math.inf
+    th2 = B.width / (R - A.width) if R > A.width else math.inf
+    return th1, th2
 
 
-def _seq_sum(v):
-    """Sum in index order (the order of the node moments' definition)."""
-    return np.cumsum(v, axis=0)[-1]
+def _pair_force(xt, xs, ms, p):
+    """Short-range accelerations [3, t] on targets xt [3, t] from sources xs
+    [3, S] of masses ms [S] (already shifted to their image)."""
+    d = xs[:, None, :] - xt[:, :, None]
+    s2 = (d * d).sum(axis=0)
+    keep = (s2 < p.rcut * p.rcut) & (s2 > 0)
+    se2 = np.where(keep, s2 + p.eps * p.eps, 1.0)
+    se = np.sqrt(se2)
+    f = np.where(keep, p.G * ms[None, :] * split_factor(se / (2.0 * p.rs)) / (se2 * se), 0.0)
+    return (f[None] * d).sum(axis=2), int(keep.sum())
 
 
-def monopole_accel(pos, mass, params, theta, min_level=2, alpha=0.0, acc_ref=None):
-    """Accelerations [3][n] (input order) with monopole acceptance, and the
-    number of (target, monopole) and (target, source particle) pairs taken.
-    theta: the geometric test (0: off); alpha > 0 adds the relative test
-    against acc_ref [3][n] (input order)."""
+def dtt_accel(pos, mass, params, theta=0.0, alpha=0.0, acc_ref=None, tree=None):
+    """Short-range accelerations [3][n] (input order) by the dual tree
+    traversal with monopole acceptance.
+
+    theta: geometric test (0: off); alpha > 0 with acc_ref [3][n] (input
+    order): the relative test.  Returns a dict with 'acc', 'n_mono_pairs'
+    (target particles x accepted monopoles), 'n_pp_pairs' (particle pairs
+    within the cut summed directly), 'accepted' (the list of (target leaf,
+    source node, shift) taken as monopoles) and 'tree'."""
     p = params
-    pos = np.asarray(pos, dtype=np.float64)
-    mass = np.asarray(mass, dtype=np.float64)
-    n = pos.shape[1]
-    L, bits = p.L, p.key_bits
-    W = 1 << bits
-    T = int(np.ceil((p.rcut * W / L) ** 2))
-    emax = int(np.floor(2.0 * p.rcut * W / L))
-    keys = hilbert_keys(pos, L, bits)
-    order = sort_order(keys)
-    sk = keys[order]
-    wpos = np.mod(pos, L)[:, order]
-    m_s = mass[order]
-    q = quantise(pos[:, order], L, bits)
-    lv = leaves(sk, bits, p.leaf_max)
-    llo, lhi = leaf_boxes(q, lv)
-    lbeg, lcnt = lv["begin"], lv["count"]
-    nleaf = lbeg.size
-    # the source hierarchy
-    cnt = [nleaf]
-    while cnt[-1] > 1:
-        cnt.append((cnt[-1] + 7) // 8)
-    boxes_lo, boxes_hi, nmass, ncom = [llo.T.copy()], [lhi.T.copy()], [], []
-    lm = np.array([_seq_sum(m_s[b:b + c]) for b, c in zip(lbeg, lcnt)])
-    lx = np.array([(m_s[b:b + c] * wpos[:, b:b + c]).sum(1) for b, c in zip(lbeg, lcnt)]).reshape(-1, 3)
-    nmass.append(lm)
-    ncom.append(lx)                      # sum of m x for now
-    for h in range(1, len(cnt)):
-        lo = np.empty((cnt[h], 3), dtype=np.int64)
-        hi = np.empty((cnt[h], 3), dtype=np.int64)
-        mm = np.empty(cnt[h])
-        mx = np.empty((cnt[h], 3))
-        for i in range(cnt[h]):
-            a, b = 8 * i, min(8 * i + 8, cnt[h - 1])
-            lo[i] = boxes_lo[h - 1][a:b].min(0)
-            hi[i] = boxes_hi[h - 1][a:b].max(0)
-            mm[i] = _seq_sum(nmass[h - 1][a:b])
-            mx[i] = ncom[h - 1][a:b].sum(0)
-        boxes_lo.append(lo)
-        boxes_hi.append(hi)
-        nmass.append(mm)
-        ncom.append(mx)
-    com = [mx / np.where(mm > 0, mm, 1.0)[:, None] for mm, mx in zip(nmass, ncom)]
-    top = len(cnt) - 1
-    shifts = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
-    acc_s = np.zeros((3, n))
-    n_mono = 0
-    n_pp = 0
-    ell2 = p.eps * p.eps
+    if tree is None:
+        tree = Tree(pos, mass, p)
+    n = tree.n
+    acc_sorted = np.zeros((3, n))
+    out = {"acc": np.zeros((3, n)), "n_mono_pairs": 0, "n_pp_pairs": 0, "accepted": [], "tree": tree}
+    if n == 0:
+        return out
+    amag = None
     if alpha > 0:
-        ar = np.asarray(acc_ref, dtype=np.float64)[:, order]
-        amag2 = (ar[0] * ar[0] + ar[1] * ar[1]) + ar[2] * ar[2]
-    cell = L / float(W)
-    for start, count, alo, ahi in _blocks(q, n, emax):
-        mono, ppl = [], []
-        a2 = float(amag2[start:start + count].min()) if alpha > 0 else 0.0
+        ar = np.asarray(acc_ref, dtype=np.float64)[:, tree.order]
+        amag = np.sqrt((ar * ar).sum(axis=0))
+    rc2 = p.rcut * p.rcut
+    L = tree.L
 
-        def visit(h, i, s):
-            rel = (p.G, float(nmass[h][i]), cell, alpha, a2) if alpha > 0 else None
-            if h >= min_level and (theta > 0 or alpha > 0) and \
-                    _accept(alo, ahi, boxes_lo[h][i], boxes_hi[h][i], s, W, theta, rel):
-                mono.append((h, i, s))
-                return
-            if h == 0:
-                ppl.append((i, s))
-                return
-            for c in range(8 * i, min(8 * i + 8, cnt[h - 1])):
-                if _gap2(alo, ahi, boxes_lo[h - 1][c], boxes_hi[h - 1][c], s, W) < T:
-                    visit(h - 1, c, s)
+    def accept(a, b, s, xt):
+        if theta <= 0 and alpha <= 0:
+            return False
+        if s == (0, 0, 0) and tree.contains(b, a):
+            return False
+        if theta > 0:
+            th1, th2 = opening_angles(tree, a, b, s)
+            if not (th1 <= theta and th2 <= theta):
+                return False
+        if alpha > 0:
+            B = tree.nodes[b]
+            A = tree.nodes[a]
+            c = B.com + L * np.asarray(s, dtype=np.float64)
+            sd = np.sqrt(((xt - c[:, None]) ** 2).sum(axis=0))
+            if np.any(sd <= 0):
+                return False
+            lhs = p.G * B.mass / sd ** 2 * (B.width / sd) ** 2
+            if not np.all(lhs <= alpha * amag[A.begin:A.end]):
+                return False
+        return True
 
-        for s in shifts:
-            if _gap2(alo, ahi, boxes_lo[top][0], boxes_hi[top][0], s, W) < T:
-                visit(top, 0, s)
-        xi = wpos[:, start:start + count]                        # [3, t]
-        src, sm = [], []
-        for leaf, s in ppl:
-            b, c = lbeg[leaf], lcnt[leaf]
-            src.append(wpos[:, b:b + c] + L * np.array(s, dtype=np.float64)[:, None])
-            sm.append(m_s[b:b + c])
-        for h, i, s in mono:
-            src.append(com[h][i][:, None] + L * np.array(s, dtype=np.float64)[:, None])
-            sm.append(np.array([nmass[h][i]]))
-        if not src:
-            continue
-        xs = np.concatenate(src, axis=1)                         # [3, S]
-        ms = np.concatenate(sm)
-        d = xs[:, None, :] - xi[:, :, None]                      # [3, t, S]
-        s2 = (d * d).sum(0)
-        keep = (s2 < p.rcut * p.rcut) & (s2 > 0)
-        se2 = s2 + ell2
-        se = np.sqrt(np.where(keep, se2, 1.0))
-        f = np.where(keep, p.G * ms[None, :] * _split(se / (2 * p.rs)) / (se2 * se), 0.0)
-        acc_s[:, start:start + count] = (f[None] * d).sum(2)
-        n_mono += count * len(mono)
-        n_pp += int(keep[:, :-len(mono) or None].sum()) if mono else int(keep.sum())
-    acc = np.zeros((3, n))
-    acc[:, order] = acc_s
-    return {"acc": acc, "n_mono_pairs": n_mono, "n_pp_pairs": n_pp}
+    for a in tree.leaves():
+        A = tree.nodes[a]
+        xt = tree.x[:, A.begin:A.end]
+        pp_x, pp_m, mono_x, mono_m = [], [], [], []
+        for s in SHIFTS:
+            sh = L * np.asarray(s, dtype=np.float64)
+            stack = [tree.root]
+            while stack:
+                b = stack.pop()
+                if tree.cube_gap2(a, b, s) >= rc2:
+                    continue
+                B = tree.nodes[b]
+                if accept(a, b, s, xt):
+                    out["accepted"].append((a, b, s))
+                    mono_x.append((B.com + sh)[:, None])
+                    mono_m.append(np.array([B.mass]))
+                elif B.leaf:
+                    pp_x.append(tree.x[:, B.begin:B.end] + sh[:, None])
+                    pp_m.append(tree.m[B.begin:B.end])
+                else:
+                    stack.extend(B.children)
+        if pp_x:
+            f, kept = _pair_force(xt, np.concatenate(pp_x, axis=1), np.concatenate(pp_m), p)
+            acc_sorted[:, A.begin:A.end] += f
+            out["n_pp_pairs"] += kept
+        if mono_x:
+            f, _ = _pair_force(xt, np.concatenate(mono_x, axis=1), np.concatenate(mono_m), p)
+            acc_sorted[:, A.begin:A.end] += f
+            out["n_mono_pairs"] += len(mono_x) * (A.end - A.begin)
+    out["acc"][:, tree.order] = acc_sorted
+    return out

@@ -107,11 +107,21 @@ constexpr double csqrt(double x) {
 }
 // (U_MAX / 2)^(3/2): H's factor in the length unit ell
 constexpr double kHScale = 0.5 * SPLIT_POLY_U_MAX * csqrt(0.5 * SPLIT_POLY_U_MAX);
-static_assert(SPLIT_POLY_DEGREE == 9, "the pair function unrolls a degree-9 polynomial");
-#define PP_HC(j) ((float)(kHScale * SPLIT_POLY_C[j]))
+// H's coefficients times (U_MAX / 2)^(3/2), rounded once to FP32: the pair
+// loop's literal operands
+struct HCoef {
+    float c[SPLIT_POLY_DEGREE + 1];
+};
+constexpr HCoef make_hcoef() {
+    HCoef h{};
+    for (int j = 0; j <= SPLIT_POLY_DEGREE; ++j) h.c[j] = (float)(kHScale * SPLIT_POLY_C[j]);
+    return h;
+}
+constexpr HCoef kHC = make_hcoef();
 
-// (U_max/2)^{3/2} H(u) at r2 = s_eps^2 / ell^2: the degree-9 polynomial in
-// t = r2 - 1, or (TABLE) the interpolated table of the paper's design: kTabN
+// (U_max/2)^{3/2} H(u) at r2 = s_eps^2 / ell^2: the polynomial in t = r2 - 1
+// (Horner, one FMA per degree), or (TABLE) the interpolated table of the
+// paper's design: kTabN
 // quadratic pieces over r2 in [0, 2), each stored as (a, b, c) with
 // h = a + z (b + z c), z the position inside the piece.  Past r2 = 2 the
 // last piece is extrapolated; such pairs lie beyond the cut and are masked.
@@ -128,15 +138,10 @@ __device__ __forceinline__ float split_h(float r2, const float4* __restrict__ ta
         return fmaf(fmaf(c.z, z, c.y), z, c.x);
     }
     const float t = r2 - 1.f;
-    float h = fmaf(t, PP_HC(9), PP_HC(8));
-    h = fmaf(h, t, PP_HC(7));
-    h = fmaf(h, t, PP_HC(6));
-    h = fmaf(h, t, PP_HC(5));
-    h = fmaf(h, t, PP_HC(4));
-    h = fmaf(h, t, PP_HC(3));
-    h = fmaf(h, t, PP_HC(2));
-    h = fmaf(h, t, PP_HC(1));
-    return fmaf(h, t, PP_HC(0));
+    float h = kHC.c[SPLIT_POLY_DEGREE];
+#pragma unroll
+    for (int j = SPLIT_POLY_DEGREE - 1; j >= 0; --j) h = fmaf(h, t, kHC.c[j]);
+    return h;
 }
 
 // One source against the lane's target; adds into (tx, ty, tz).

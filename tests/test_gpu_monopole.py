@@ -44,7 +44,7 @@ def rel(acc, ref):
 
 @pytest.mark.parametrize("theta", [0.3, 0.5])
 def test_monopoles_match_tree_oracle(pp, box, theta):
-    from oracle import tree
+    from tests import monopole_mirror as tree
     pos, mass, p = box
     ref = tree.monopole_accel(pos, mass.astype(np.float64), p, theta)
     plan = pp.Plan(p, pos.shape[1])
@@ -99,7 +99,7 @@ def box_ref(box, oracle_mod):
 def test_relative_criterion_matches_tree_oracle(pp, box, box_ref, theta, alpha):
     """Gadget-2's relative test against reference accelerations (here the
     exact ones, rounded to FP32 as the caller would pass them)."""
-    from oracle import tree
+    from tests import monopole_mirror as tree
     pos, mass, p = box
     acc_ref = box_ref.astype(np.float32)
     ref = tree.monopole_accel(pos, mass.astype(np.float64), p, theta, alpha=alpha, acc_ref=acc_ref)
