@@ -27,13 +27,13 @@ sys.path.insert(0, ROOT)
 METRIC = "PP pair-interactions/s and % FP32 VALU peak; batched vs plain at fixed error"
 # FP32 operations the PP kernel performs per evaluated pair (an FMA counts 2):
 # 3 sub (d), 3 FMA (s^2 + eps^2), 1 rsqrt, 1 sub (polynomial variable t),
-# 8 FMA (degree-8 polynomial), 1 mul + 1 FMA (y^3 - H), 3 FMA (sum) = 36;
-# boxes whose masses differ add 1 mul (the source mass) = 37.  Compares and
+# 9 FMA (degree-9 polynomial), 1 mul + 1 FMA (y^3 - H), 3 FMA (sum) = 38;
+# boxes whose masses differ add 1 mul (the source mass) = 39.  Compares and
 # selects are not counted; the compensated sum is amortised over 64-pair
 # tiles.  The hardware FP32 flop counter, per evaluated lane-pair, is the
 # cross-check (it also sees the FP32 work of staging the sources).
-FLOPS_EQUAL_MASS = 36
-FLOPS_GENERAL = 37
+FLOPS_EQUAL_MASS = 38
+FLOPS_GENERAL = 39
 PAPER_FLOPS_PER_INTERACTION = 22      # convention of sec. 5 (Newtonian pair count)
 FP32_VECTOR_PEAK = 157.3e12           # MI355X, 256 CU x 2.4 GHz x 256 flop/clk
 # HBM bytes per PP-kernel launch on the headline workload, from rocprofv3

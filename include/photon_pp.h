@@ -185,7 +185,9 @@ typedef struct pp_stats {
 } pp_stats;
 /* Waits for the last PP kernel when timing is on.                          */
 /* Monopole acceptance (sec. 3.3, the 1-to-N case of the dual tree walk) for
- * pp_accel on this plan: a source tree node of 64 leaves or more whose box
+ * pp_accel on this plan.  The target block is kept (the policy sec. 3.3
+ * takes on MIC) and the source tree is opened: a source node of any level
+ * (a single leaf, a group of 8 consecutive leaves, or larger) whose box
  * satisfies (A + B) / R <= theta against the target block (A, B the longest
  * box sides, R the distance of the box centres; this implies
  * B / (R - A) <= theta) acts through its mass at its centre of mass, with
@@ -259,7 +261,35 @@ int pp_autotune(pp_plan* plan, const double* pos, const float* mass, int64_t n,
  * Synchronises the stream.                                                 */
 int pp_count_interactions(pp_plan* plan, int64_t* counts, int64_t* total, void* stream);
 
-/* ------------------------------------------------------------- batches --
+/* The per-block source lists of the last pp_accel / pp_accel_active /
+ * pp_accel_f64 call on this plan, as the PP kernels read them: the N-to-M
+ * leaf lists of the dual tree traversal (sec. 3.3) gathered per target
+ * block.  A target block is a run of consecutive particles in key order
+ * (at most 64, inside one 64-particle chunk of the box, integer bounding box
+ * at most floor(2 rcut 2^b / L) cells wide per axis); its list is a sequence
+ * of ranges, each a run of whole consecutive leaves taken at one periodic
+ * shift, holding every leaf whose integer box passes the near-pair test of
+ * pp_near_pairs against the block's box, each (leaf, shift) once.
+ *   pp_plan_lists_size: nblock, nrange (either may be NULL).
+ *   pp_plan_lists_export (host or device destinations, any may be NULL):
+ *     perm   [n] int32: input index of the k-th particle in key order
+ *     bstart, bcount [nblock] int32: block b holds key-ordered particles
+ *            bstart[b] .. bstart[b] + bcount[b] - 1
+ *     blo, bhi [3][nblock] int32: its integer bounding box, hi exclusive
+ *     roff   [nblock + 1] int64: block b's ranges are roff[b] .. roff[b+1]-1
+ *     slen   [nblock] int32: the number of sources in block b's list
+ *     rbeg   [nrange] int32: first particle (key order) of the range
+ *     rpre   [nrange] int32: list position of the range's first particle
+ *            within its block's list (ranges ascend; a range ends where the
+ *            next one of its block starts, the last at slen[b])
+ *     rcode  [nrange] uint8: shift code 9 (s_x + 1) + 3 (s_y + 1) + (s_z + 1)
+ * Synchronous.  PP_EINVAL when the plan has no lists yet.                   */
+int pp_plan_lists_size(const pp_plan* plan, int64_t* nblock, int64_t* nrange);
+int pp_plan_lists_export(const pp_plan* plan, int32_t* perm, int32_t* bstart, int32_t* bcount,
+                         int32_t* blo, int32_t* bhi, int64_t* roff, int32_t* slen, int32_t* rbeg,
+                         int32_t* rpre, uint8_t* rcode);
+
+/* ------------------------------------------------------------- batches --/* ------------------------------------------------------------- batches --
  * Many independent periodic boxes of different N, L and split parameters in
  * one pass (the task-queue idea of sec. 4.3 taken to whole boxes): every
  * stage runs once over all boxes, and the PP kernel is one persistent,

@@ -50,6 +50,8 @@ def _load():
     lib.oracle_leaves.argtypes = [P, i64, i32, i32, i64, P, P, P, P]
     lib.oracle_leaf_boxes.restype = None
     lib.oracle_leaf_boxes.argtypes = [P, i64, P, P, i64, P, P]
+    lib.oracle_neighbours.restype = i64
+    lib.oracle_neighbours.argtypes = [P, i64, dbl, dbl, P, i64, i64, P, P, P]
     lib.oracle_near_pairs.restype = i64
     lib.oracle_near_pairs.argtypes = [P, P, i64, dbl, dbl, i32, P, i64, i64, P, P, P]
     _lib = lib
@@ -192,6 +194,33 @@ def near_pairs(lo, hi, L, rcut, bits=21, rows=None):
             raise ValueError(f"oracle_near_pairs failed ({tot})")
         if tot <= cap:
             return row_ptr, src[:tot].copy(), code[:tot].copy()
+        cap = int(tot)
+
+
+def neighbours(pos, params, targets=None):
+    """In-cut neighbours (FP64 s < r_cut, minimum image, j != i) of the
+    targets (all particles by default): (row_ptr, nbr, code) with the
+    neighbours of target t in nbr[row_ptr[t]:row_ptr[t + 1]] (ascending) and
+    code the image's shift code 9 (s_x + 1) + 3 (s_y + 1) + (s_z + 1)."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[1]
+    if targets is None:
+        tp, nt = None, n
+    else:
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        tp, nt = _p(targets), targets.size
+    row_ptr = np.zeros(nt + 1, dtype=np.int64)
+    cap = 1 << 20
+    while True:
+        nbr = np.zeros(cap, dtype=np.int64)
+        code = np.zeros(cap, dtype=np.uint8)
+        tot = lib.oracle_neighbours(_p(pos), n, float(params.L), float(params.rcut), tp, nt, cap,
+                                    _p(row_ptr), _p(nbr), _p(code))
+        if tot < 0:
+            raise ValueError(f"oracle_neighbours failed ({tot})")
+        if tot <= cap:
+            return row_ptr, nbr[:tot].copy(), code[:tot].copy()
         cap = int(tot)
 
 

@@ -172,6 +172,70 @@ int oracle_accel(const double* pos, const double* mass, int64_t n,
     return ORACLE_OK;
 }
 
+/*
+ * The in-cut neighbours of the requested targets: every j != i with FP64
+ * s < r_cut at the minimum periodic image, decided exactly as oracle_accel
+ * decides which pairs it keeps, with the image's shift code
+ * c = 9 (s_x + 1) + 3 (s_y + 1) + (s_z + 1), where s = (x_j + s L) - x_i is
+ * the minimum-image separation of the wrapped positions.
+ *   row_ptr  out [nt + 1]: the neighbours of target t are entries
+ *            row_ptr[t] .. row_ptr[t + 1] - 1, in ascending j
+ *   nbr, code out [cap]: neighbour index and shift code
+ * Returns the total number of neighbours (entries are written only when it
+ * is at most cap), or a negative error.
+ */
+static int shift_of(double d, double L)
+{
+    if (d > 0.5 * L) return -1;
+    if (d < -0.5 * L) return 1;
+    return 0;
+}
+
+int64_t oracle_neighbours(const double* pos, int64_t n, double L, double rcut,
+                          const int64_t* targets, int64_t nt, int64_t cap,
+                          int64_t* row_ptr, int64_t* nbr, uint8_t* code)
+{
+    if (n < 0 || nt < 0 || !(L > 0) || !(rcut > 0) || !(rcut < 0.5 * L)) return ORACLE_EINVAL;
+    if (!targets && nt != n) return ORACLE_EINVAL;
+    double* w = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!w) return ORACLE_ENOMEM;
+    for (int64_t k = 0; k < 3 * n; ++k) w[k] = wrap(pos[k], L);
+    const double* wx = w;
+    const double* wy = w + n;
+    const double* wz = w + 2 * n;
+    const double rcut2 = rcut * rcut;
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nt; ++t) {
+            int64_t i = targets ? targets[t] : t;
+            int64_t k = pass ? row_ptr[t] : 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double ex = wx[j] - wx[i], ey = wy[j] - wy[i], ez = wz[j] - wz[i];
+                double dx = min_image(ex, L);
+                double dy = min_image(ey, L);
+                double dz = min_image(ez, L);
+                double s2 = dx * dx + dy * dy + dz * dz;
+                if (!(s2 < rcut2)) continue;
+                if (pass) {
+                    nbr[k] = j;
+                    code[k] = (uint8_t)(9 * (shift_of(ex, L) + 1) + 3 * (shift_of(ey, L) + 1) +
+                                        (shift_of(ez, L) + 1));
+                }
+                ++k;
+            }
+            if (!pass) row_ptr[t + 1] = k;
+        }
+        if (!pass) {
+            row_ptr[0] = 0;
+            for (int64_t t = 0; t < nt; ++t) row_ptr[t + 1] += row_ptr[t];
+            if (row_ptr[nt] > cap) break;
+        }
+    }
+    free(w);
+    return row_ptr[nt];
+}
+
 /* ---------------------------------------------------------------------------
  * Peano-Hilbert keys.
  *

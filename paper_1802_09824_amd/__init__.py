@@ -76,6 +76,8 @@ _SIGS = {
     "pp_accel_active": (_i32, [_P, _P, _P, _i64, _P, _P, _P]),
     "pp_plan_set_monopole_relative": (_i32, [_P, C.c_double, _P, _i64, _P]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
+    "pp_plan_lists_size": (_i32, [_P, C.POINTER(_i64), C.POINTER(_i64)]),
+    "pp_plan_lists_export": (_i32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pp_plan_set_timing": (_i32, [_P, _i32]),
     "pp_plan_get_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
     "pp_plan_set_tuning": (_i32, [_P, C.POINTER(pp_tuning)]),
@@ -314,6 +316,28 @@ class Plan:
                                 cache_path.encode() if cache_path else None, _stream(stream)),
                "pp_autotune")
         return self.get_tuning()
+
+    def export_lists(self) -> dict:
+        """The per-block source lists of the last accel call (host arrays)."""
+        import numpy as np
+        nb, nr = _i64(0), _i64(0)
+        _check(_lib.pp_plan_lists_size(self._h, C.byref(nb), C.byref(nr)), "pp_plan_lists_size")
+        nb, nr = int(nb.value), int(nr.value)
+        n = self.stats()["n"]
+        out = {"perm": np.zeros(max(n, 1), np.int32), "bstart": np.zeros(max(nb, 1), np.int32),
+               "bcount": np.zeros(max(nb, 1), np.int32), "blo": np.zeros((3, max(nb, 1)), np.int32),
+               "bhi": np.zeros((3, max(nb, 1)), np.int32), "roff": np.zeros(nb + 1, np.int64),
+               "slen": np.zeros(max(nb, 1), np.int32), "rbeg": np.zeros(max(nr, 1), np.int32),
+               "rpre": np.zeros(max(nr, 1), np.int32), "rcode": np.zeros(max(nr, 1), np.uint8)}
+        _check(_lib.pp_plan_lists_export(self._h, *(a.ctypes.data_as(_P) for a in out.values())),
+               "pp_plan_lists_export")
+        for k in ("bstart", "bcount", "slen"):
+            out[k] = out[k][:nb]
+        out["blo"], out["bhi"] = out["blo"][:, :nb], out["bhi"][:, :nb]
+        for k in ("rbeg", "rpre", "rcode"):
+            out[k] = out[k][:nr]
+        out["perm"] = out["perm"][:n]
+        return out
 
     def count_interactions(self, per_target: bool = False, stream=None):
         tot = _i64(0)

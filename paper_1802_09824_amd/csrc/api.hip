@@ -810,6 +810,47 @@ int pp_plan_set_tuning(pp_plan* pl, const pp_tuning* t) {
     return PP_OK;
 }
 
+static int lists_size(const Batch& b, int64_t* nblock, int64_t* nrange) {
+    if (!b.lists_valid) return fail(PP_EINVAL, "no lists: call the accel function first");
+    if (nblock) *nblock = b.w.nblock;
+    if (nrange) *nrange = b.w.nrange;
+    return PP_OK;
+}
+
+static int lists_export(const Batch& b, int32_t* perm, int32_t* bstart, int32_t* bcount, int32_t* blo,
+                        int32_t* bhi, int64_t* roff, int32_t* slen, int32_t* rbeg, int32_t* rpre,
+                        uint8_t* rcode) {
+    PP_TRY(lists_size(b, nullptr, nullptr));
+    const Work& w = b.w;
+    const int64_t nb = w.nblock, nr = w.nrange, n = w.pos_n;
+    PP_HIP(hipDeviceSynchronize());
+    if (perm && n > 0) PP_HIP(hipMemcpy(perm, w.perm.p, 4 * n, hipMemcpyDefault));
+    if (nb > 0) {
+        if (bstart) PP_HIP(hipMemcpy(bstart, w.bstart.p, 4 * nb, hipMemcpyDefault));
+        if (bcount) PP_HIP(hipMemcpy(bcount, w.bcount.p, 4 * nb, hipMemcpyDefault));
+        if (slen) PP_HIP(hipMemcpy(slen, w.slen.p, 4 * nb, hipMemcpyDefault));
+        if (blo || bhi) {
+            std::vector<IBox> hb(nb);
+            PP_HIP(hipMemcpy(hb.data(), w.bbox.p, sizeof(IBox) * nb, hipMemcpyDeviceToHost));
+            std::vector<int32_t> t(3 * nb);
+            for (int k = 0; k < 2; ++k) {
+                int32_t* dst = k == 0 ? blo : bhi;
+                if (!dst) continue;
+                for (int64_t x = 0; x < nb; ++x)
+                    for (int ax = 0; ax < 3; ++ax) t[ax * nb + x] = k == 0 ? hb[x].lo[ax] : hb[x].hi[ax];
+                PP_HIP(hipMemcpy(dst, t.data(), 4 * 3 * nb, hipMemcpyDefault));
+            }
+        }
+    }
+    if (roff) PP_HIP(hipMemcpy(roff, w.roff.p, 8 * (nb + 1), hipMemcpyDefault));
+    if (nr > 0) {
+        if (rbeg) PP_HIP(hipMemcpy(rbeg, w.rbeg.p, 4 * nr, hipMemcpyDefault));
+        if (rpre) PP_HIP(hipMemcpy(rpre, w.rpre.p, 4 * nr, hipMemcpyDefault));
+        if (rcode) PP_HIP(hipMemcpy(rcode, w.rcode.p, nr, hipMemcpyDefault));
+    }
+    return PP_OK;
+}
+
 static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStream_t s) {
     if (!b.lists_valid) return fail(PP_EINVAL, "no lists: call the accel function first");
     if (b.lists_mono)
@@ -827,6 +868,18 @@ static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStre
     *total = (int64_t)h;
     b.st.interactions = (int64_t)h;
     return PP_OK;
+}
+
+int pp_plan_lists_size(const pp_plan* pl, int64_t* nblock, int64_t* nrange) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    return lists_size(pl->b, nblock, nrange);
+}
+
+int pp_plan_lists_export(const pp_plan* pl, int32_t* perm, int32_t* bstart, int32_t* bcount,
+                         int32_t* blo, int32_t* bhi, int64_t* roff, int32_t* slen, int32_t* rbeg,
+                         int32_t* rpre, uint8_t* rcode) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    return lists_export(pl->b, perm, bstart, bcount, blo, bhi, roff, slen, rbeg, rpre, rcode);
 }
 
 int pp_count_interactions(pp_plan* pl, int64_t* counts, int64_t* total, void* stream) {

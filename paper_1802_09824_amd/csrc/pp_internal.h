@@ -152,6 +152,12 @@ struct Work {
     DevBuf tree_mc;          // double4 per tree node: sum m x, sum m y, sum m z, sum m
     DevBuf blk_amin2;        // double per block: min |a_ref|^2 over its targets
     const FEntry* ent_final = nullptr;   // the list expansion's final entries (nentry)
+    // monopoles accepted by the depth-first walk, per final entry (null when
+    // acceptance is off): leaves (bit = leaf - the entry's first leaf) and
+    // groups of 8 leaves (bit = group - the entry's first group)
+    DevBuf mono0_e, mono1_e;
+    const uint64_t* mono0 = nullptr;
+    const uint8_t* mono1 = nullptr;
     const uint8_t* active = nullptr;     // the items' target flags (null: every target)
     std::vector<int64_t> lvl_prefix_host;
     DevBuf sort_ws, scan_ws, sort_tmp;

@@ -443,19 +443,24 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
 }
 
 // Monopoles (sec. 3.3, 1 to N): one wave per target block walks the block's
-// entries of the list expansion; accepted nodes become sources of their
-// mass at their centre of mass (FP64 sums, shifted by their periodic
-// image, relative to the FP64 block centre, in units of ell) and go through
-// the same pair arithmetic as particles, with the same cut.  The result is
-// added to the accelerations the PP path wrote.
+// entries of the list expansion in order.  An entry contributes the node it
+// stands for when the breadth-first expansion accepted it, and the leaves and
+// groups of 8 leaves the depth-first walk accepted under it.  Each accepted
+// node becomes a source of its mass at its centre of mass (FP64 sums,
+// shifted by its periodic image, relative to the FP64 block centre, in units
+// of ell), staged into an LDS ring like the particles of pp_item and swept
+// with the same pair arithmetic and the same cut.  The result is added to
+// the accelerations the PP path wrote.
 __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry* __restrict__ ent,
                                                       const int64_t* __restrict__ eoff,
+                                                      const uint64_t* __restrict__ mono0,
+                                                      const uint8_t* __restrict__ mono1,
                                                       const TreeView* __restrict__ tvs,
                                                       const double4* __restrict__ mc,
                                                       const double* __restrict__ pos_s, int64_t N,
                                                       int64_t nblock,
                                                       unsigned long long* __restrict__ counter) {
-    __shared__ float4 tile[kBlock];
+    __shared__ float4 tile[2 * kBlock];
     const int64_t b = blockIdx.x;
     if (b >= nblock) return;
     if (ia.ioff[b + 1] == ia.ioff[b]) return;        // a block without active targets
@@ -478,41 +483,74 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
         zi = (float)((pos_s[2 * N + t] - oz) * inv_len);
     }
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    int count = 0;
     int64_t taken = 0;
-    const int64_t e_end = eoff[b + 1];
-    for (int64_t e0 = eoff[b]; e0 < e_end; e0 += kBlock) {
-        const int64_t e = e0 + lane;
+    // stage this lane's node (level, index) under shift code sc if `on`
+    auto stage = [&](bool on, int lev, int64_t node, int sc) {
         bool keep = false;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (e < e_end) {
-            const FEntry E = ent[e];
-            if (E.mono) {
-                const double4 m = mc[tv.off[E.lev] + E.node];
-                if (m.w > 0.0) {
-                    keep = true;
-                    const double sx = (double)(E.sc / 9 - 1) * L;
-                    const double sy = (double)((E.sc / 3) % 3 - 1) * L;
-                    const double sz = (double)(E.sc % 3 - 1) * L;
-                    v.x = (float)((m.x / m.w + sx - ox) * inv_len);
-                    v.y = (float)((m.y / m.w + sy - oy) * inv_len);
-                    v.z = (float)((m.z / m.w + sz - oz) * inv_len);
-                    v.w = (float)m.w;
-                }
+        if (on) {
+            const double4 m = mc[tv.off[lev] + node];
+            if (m.w > 0.0) {
+                keep = true;
+                const double sx = (double)(sc / 9 - 1) * L;
+                const double sy = (double)((sc / 3) % 3 - 1) * L;
+                const double sz = (double)(sc % 3 - 1) * L;
+                v.x = (float)((m.x / m.w + sx - ox) * inv_len);
+                v.y = (float)((m.y / m.w + sy - oy) * inv_len);
+                v.z = (float)((m.z / m.w + sz - oz) * inv_len);
+                v.w = (float)m.w;
             }
         }
         const uint64_t bal = __ballot(keep);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (keep) tile[rank] = v;
-        const int cnt = __popcll(bal);
-        taken += cnt;
+        if (keep) tile[count + rank] = v;
+        const int got = __popcll(bal);
+        count += got;
+        taken += got;
+        if (count >= kBlock) {
+            wave_sync();
+            float tx = 0.f, ty = 0.f, tz = 0.f;
+            for (int q = 0; q < kBlock; ++q) pair_f32<false>(tile[q], xi, yi, zi, P, tx, ty, tz);
+            kahan_add(ax, cx, tx);
+            kahan_add(ay, cy, ty);
+            kahan_add(az, cz, tz);
+            wave_sync();
+            count -= kBlock;
+            if (lane < count) tile[lane] = tile[kBlock + lane];
+            wave_sync();
+        }
+    };
+    const int64_t e_end = eoff[b + 1];
+    // nodes the breadth-first expansion accepted: one per entry, 64 entries
+    // at a time
+    for (int64_t e0 = eoff[b]; e0 < e_end; e0 += kBlock) {
+        const int64_t e = e0 + lane;
+        FEntry E{};
+        const bool in = e < e_end;
+        if (in) E = ent[e];
+        stage(in && E.mono, E.lev, E.node, E.sc);
+    }
+    // leaves and groups of 8 leaves the depth-first walk accepted
+    if (mono0) {
+        for (int64_t e = eoff[b]; e < e_end; ++e) {
+            const uint64_t m0 = mono0[e];
+            const uint32_t m1 = mono1[e];
+            if ((m0 | m1) == 0) continue;
+            const FEntry E = ent[e];
+            const int64_t first = (int64_t)E.node << (3 * E.lev);
+            if (m0) stage((m0 >> lane) & 1ull, 0, first + lane, E.sc);
+            if (m1) stage(lane < 8 && ((m1 >> lane) & 1u), 1, (first >> 3) + lane, E.sc);
+        }
+    }
+    if (count > 0) {
         wave_sync();
         float tx = 0.f, ty = 0.f, tz = 0.f;
-        for (int q = 0; q < cnt; ++q) pair_f32<false>(tile[q], xi, yi, zi, P, tx, ty, tz);
+        for (int q = 0; q < count; ++q) pair_f32<false>(tile[q], xi, yi, zi, P, tx, ty, tz);
         kahan_add(ax, cx, tx);
         kahan_add(ay, cy, ty);
         kahan_add(az, cz, tz);
-        wave_sync();
     }
     if (taken == 0) return;
     if (lane < nt && target_on(ia, ia.perm[t])) {
@@ -876,8 +914,8 @@ int launch_monopole(const BatchDev& bd, const Work& w, float* acc, unsigned long
     ItemArgs ia = item_args(bd, w, 0);
     ia.acc = acc;
     hipLaunchKernelGGL(monopole_kernel, dim3((unsigned)w.nblock), dim3(kBlock), 0, s, ia, w.ent_final,
-                       w.eoff.as<int64_t>(), w.tviews.as<TreeView>(), w.tree_mc.as<double4>(),
-                       w.pos_s.as<double>(), w.pos_n, w.nblock, counter);
+                       w.eoff.as<int64_t>(), w.mono0, w.mono1, w.tviews.as<TreeView>(),
+                       w.tree_mc.as<double4>(), w.pos_s.as<double>(), w.pos_n, w.nblock, counter);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }

@@ -549,9 +549,10 @@ __global__ void __launch_bounds__(64) block_split_kernel(
 // 8-child test per entry.  Leaves (or inside intervals) come in ascending order and
 // consecutive ones merge into one range of source particles.
 constexpr int kDfsLevel = 2;
-// Monopoles are taken for nodes of this level and up (groups of 64 leaves
-// and more), which the breadth-first expansion always reaches.
-constexpr int kMonoMinLevel = 2;
+// Monopoles may be taken at every level: by the breadth-first expansion for
+// nodes of level 2 and up, by the depth-first walk for groups of 8 leaves
+// (level 1) and single leaves (level 0).
+constexpr int kMonoMinLevel = 0;
 
 
 // Test the children of (h, i): pass bits and inside bits (inside implies pass).
@@ -675,13 +676,22 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                               int32_t* __restrict__ rcnt, int32_t* __restrict__ scnt,
                               const int64_t* __restrict__ roff, const int64_t* __restrict__ soff,
                               const int64_t* __restrict__ eoff, int32_t* __restrict__ rbeg,
-                              int32_t* __restrict__ rpre, uint8_t* __restrict__ rcode) {
+                              int32_t* __restrict__ rpre, uint8_t* __restrict__ rcode,
+                              MonoDev mono, uint64_t* __restrict__ mono0,
+                              uint8_t* __restrict__ mono1) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= F) return;
     const FEntry E = ent[e];
     const int x = bboxid[E.blk];
     const TreeView& tv = tvs[x];
     const int64_t nleaf = tv.cnt[0];
+    // with monopole acceptance on (count pass), children met by the walk are
+    // tested too: accepted leaves go to mono0 (bit = leaf - first leaf of the
+    // entry), accepted groups of 8 leaves to mono1 (bit = group - first
+    // group), and are not listed
+    const bool mono_on = !FILL && (mono.theta2 > 0.0 || mono.alpha > 0.0);
+    uint64_t m0 = 0;
+    uint32_t m1 = 0;
     int64_t o = FILL ? roff[e] : 0;
     int64_t pos = FILL ? soff[e] - soff[eoff[E.blk]] : 0;
     int32_t nr = 0;
@@ -703,9 +713,10 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
     const int64_t first = (int64_t)E.node << (3 * E.lev);
     int64_t last = (((int64_t)E.node + 1) << (3 * E.lev)) - 1;
     if (last > nleaf - 1) last = nleaf - 1;
+    const bool walk_inside = mono.theta2 > 0.0 || mono.alpha > 0.0;   // inside nodes are opened too
     if (E.mono) {
         // a monopole: no source ranges
-    } else if (E.inside || E.lev == 0) {
+    } else if (E.lev == 0 || (E.inside && !walk_inside)) {
         emit(first, last);
     } else {
         uint64_t mask = 0;
@@ -736,7 +747,15 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                 const uint32_t w2 = wv & ~(1u << c);
                 st = (st & ~(0xffffull << (16 * (lev & 3)))) | ((uint64_t)w2 << (16 * (lev & 3)));
                 const int64_t child = 8 * node + c;
-                if (lev == 1 || ((wv >> 8) >> c & 1u)) {
+                if (mono_on) {
+                    const int64_t g = tv.off[lev - 1] + child;
+                    if (accept_monopole(A, nodes[g], s, W, mono, g, E.blk, bd.box[x].G, bd.box[x].cell)) {
+                        if (lev == 1) m0 |= 1ull << (child - first);
+                        else m1 |= 1u << (child - (first >> 3));
+                        continue;
+                    }
+                }
+                if (lev == 1 || (!walk_inside && ((wv >> 8) >> c & 1u))) {
                     const int64_t l0 = child << (3 * (lev - 1));
                     int64_t l1 = ((child + 1) << (3 * (lev - 1))) - 1;
                     if (l1 > nleaf - 1) l1 = nleaf - 1;
@@ -763,6 +782,10 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
     if (!FILL) {
         rcnt[e] = nr;
         scnt[e] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
+        if (mono0) {
+            mono0[e] = m0;
+            mono1[e] = (uint8_t)m1;
+        }
     }
 }
 
@@ -1112,11 +1135,21 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.eoff.reserve(sizeof(int64_t) * (nb + 2)));
     const int64_t* lbegin = w.lbegin.as<int64_t>();
     const int32_t* lcount = w.lcount.as<int32_t>();
+    uint64_t* mono0 = nullptr;
+    uint8_t* mono1 = nullptr;
+    if (mcfg.on()) {
+        PP_TRY(w.mono0_e.reserve(sizeof(uint64_t) * (F + 1)));
+        PP_TRY(w.mono1_e.reserve(sizeof(uint8_t) * (F + 1)));
+        mono0 = w.mono0_e.as<uint64_t>();
+        mono1 = w.mono1_e.as<uint8_t>();
+    }
+    w.mono0 = mono0;
+    w.mono1 = mono1;
     hipLaunchKernelGGL(ranges_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
                        w.rcnt_e.as<int32_t>(), w.scnt_e.as<int32_t>(), (const int64_t*)nullptr,
                        (const int64_t*)nullptr, (const int64_t*)nullptr, (int32_t*)nullptr,
-                       (int32_t*)nullptr, (uint8_t*)nullptr);
+                       (int32_t*)nullptr, (uint8_t*)nullptr, mono, mono0, mono1);
     hipLaunchKernelGGL(block_entry_kernel, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, ent, F,
                        nb, w.eoff.as<int64_t>());
     PP_HIP(hipGetLastError());
@@ -1169,7 +1202,8 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                        nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
                        (int32_t*)nullptr, (int32_t*)nullptr, w.roff_e.as<int64_t>(),
                        w.soff_e.as<int64_t>(), w.eoff.as<int64_t>(), w.rbeg.as<int32_t>(),
-                       w.rpre.as<int32_t>(), w.rcode.as<uint8_t>());
+                       w.rpre.as<int32_t>(), w.rcode.as<uint8_t>(), mono, (uint64_t*)nullptr,
+                       (uint8_t*)nullptr);
     hipLaunchKernelGGL(item_fill_kernel, dim3(blocks_for(nb, 256)), dim3(256), 0, s,
                        w.icount.as<int32_t>(), w.ioff.as<int64_t>(), nb, chunk,
                        w.iblock.as<int32_t>(), w.is0.as<int32_t>());

@@ -20,7 +20,7 @@ The model, in the library's order:
   box, mass and centre of mass;
 * per target block A and periodic image s, walk the source hierarchy from
   the root: a node whose box lies at r_cut or more from A's box is skipped;
-  a node of level >= 2 is taken as a monopole when every enabled test
+  a node of any level is taken as a monopole when every enabled test
   holds: (A + B) / R <= theta (A, B the longest box sides, R the distance of
   the box centres) and G M B^2 / r^4 <= alpha |a| (M the node mass, r the gap
   between the two boxes, |a| the smallest reference acceleration among A's
@@ -100,7 +100,7 @@ def _seq_sum(v):
     return np.cumsum(v, axis=0)[-1]
 
 
-def monopole_accel(pos, mass, params, theta, min_level=2, alpha=0.0, acc_ref=None):
+def monopole_accel(pos, mass, params, theta, min_level=0, alpha=0.0, acc_ref=None):
     """Accelerations [3][n] (input order) with monopole acceptance, and the
     number of (target, monopole) and (target, source particle) pairs taken.
     theta: the geometric test (0: off); alpha > 0 adds the relative test

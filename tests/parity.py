@@ -17,9 +17,9 @@ import numpy as np
 
 # Bound on the condition-robust error e'_i of the FP32 path, from its
 # arithmetic: each pair's factor y^3 g carries the polynomial's error of g
-# (at most 8e-7, degree 8) plus the FP32 rounding of the Horner sum and of
+# (at most 1.1e-7, degree 9) plus the FP32 rounding of the Horner sum and of
 # y^3, against g(x_max) >= 0.0168 at the cut, so no pair is off by more than
-# about 7e-5 of its magnitude (5.2e-5 for the largest case found by a
+# about 7e-5 of its magnitude (1.8e-5 for the largest case found by a
 # simulation of the FP32 sequence); the compensated sums add a few ulps.
 ROBUST_MAX = 1e-4
 

@@ -215,3 +215,34 @@ def test_pair_magnitude_sum(oracle_mod):
     r = oracle_mod.accel(pos, rng.uniform(0.5, 2.0, 300), p, pair_abs=True)
     assert np.all(r["pair_abs"] >= np.linalg.norm(r["acc"], axis=0) * (1 - 1e-14))
     assert np.all((r["pair_abs"] > 0) == (r["n_inter"] > 0))
+
+
+def test_neighbours_brute_force_over_images(oracle_mod):
+    """oracle.neighbours against a brute force over all 27 periodic images:
+    j is a neighbour of i with shift s exactly when |x_j + s L - x_i| < r_cut
+    for that image (at most one image can be, since r_cut < L / 2), and the
+    counts agree with oracle.accel's."""
+    from workloads import BoxParams
+    rng = np.random.default_rng(21)
+    L = 10.0
+    pos = rng.random((3, 300)) * L
+    pos[:, :20] = pos[:, :20] * 0.05 + L - 0.3          # a clump across the corner
+    p = BoxParams(L=L, rs=1.0, rcut=4.5, eps=0.01)
+    rp, nbr, code = oracle_mod.neighbours(pos, p)
+    ref = oracle_mod.accel(pos, np.ones(300), p)
+    assert np.array_equal(np.diff(rp), ref["n_inter"])
+    w = pos - L * np.floor(pos / L)
+    sh = np.array([(c // 9 - 1, (c // 3) % 3 - 1, c % 3 - 1) for c in range(27)], dtype=np.float64)
+    for i in range(300):
+        d = w[:, None, :] + L * sh.T[:, :, None] - w[:, i][:, None, None]     # [3, 27, n]
+        s2 = (d * d).sum(axis=0)                                               # [27, n]
+        s2[:, i] = np.inf
+        c, j = np.nonzero(s2 < p.rcut ** 2)
+        order = np.argsort(j)
+        assert np.array_equal(nbr[rp[i]:rp[i + 1]], j[order]), i
+        assert np.array_equal(code[rp[i]:rp[i + 1]], c[order]), i
+    sub = np.array([3, 17, 250])
+    rps, nbs, cds = oracle_mod.neighbours(pos, p, targets=sub)
+    for t, i in enumerate(sub):
+        assert np.array_equal(nbs[rps[t]:rps[t + 1]], nbr[rp[i]:rp[i + 1]])
+        assert np.array_equal(cds[rps[t]:rps[t + 1]], code[rp[i]:rp[i + 1]])
