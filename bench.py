@@ -89,6 +89,10 @@ def parse():
                     help="skip the monopole and adaptive-KDK legs (for profiling runs)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-box batched-vs-per-box comparison (for profiling)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 16.8M precision and 134M large-box legs")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tiles instead of running the autotuner first")
     ap.add_argument("--print-sources-sha1", action="store_true",
                     help="print the SHA-1 of the PP kernel sources the traffic figure is tied to")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -193,29 +197,55 @@ def batched_error(boxes, acc_batched, per_box_targets=256, every=8):
             "max": float(e.max()) if e.size else 0.0}
 
 
-def bench_monopole_relative(plan, pos, mass, acc_exact, exact_step_ms, alpha=0.005, steps=5):
-    """Monopole acceptance with Gadget-2's relative criterion (alpha, the
-    exact FP32 accelerations as reference) on the same box: whole-step time
-    against the exact path, and the error against the exact result."""
+def drifted(pos_t, params, seed):
+    """Positions one small step later: every particle moved by 0.02 r_s per
+    axis (Gaussian), wrapped.  The step before them gives the reference
+    accelerations of the relative opening test, as in a simulation."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    step = torch.randn(pos_t.shape, generator=g, device="cuda", dtype=torch.float64) * (0.02 * params.rs)
+    return torch.remainder(pos_t + step, params.L).contiguous()
+
+
+def bench_monopoles(plan, box, pos, mass, theta=0.3, alpha=0.005, steps=3):
+    """Monopole acceptance (sec. 3.3 dual walk, Gadget-2's relative test of
+    sec. 3.1) one step after the reference accelerations were taken: the
+    exact FP32 accelerations at the current positions serve as a_ref, the
+    particles drift by a small step, and the monopole result at the new
+    positions is compared with the exact one there (all targets), and timed
+    against the exact path."""
     import numpy as np
     import torch
-    plan.set_monopole_relative(alpha, acc_exact)
-    acc = torch.empty_like(acc_exact)
-    plan.accel(pos, mass, out=acc)
+    acc_ref = plan.accel(pos, mass)                          # previous step's forces
+    pos1 = drifted(pos, box.params, 1234)
+    exact = plan.accel(pos1, mass)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        plan.accel(pos, mass, out=acc)
+        plan.accel(pos1, mass, out=exact)
+    torch.cuda.synchronize()
+    exact_ms = 1e3 * (time.perf_counter() - t0) / steps
+    plan.set_monopole(theta)
+    plan.set_monopole_relative(alpha, acc_ref)
+    acc = plan.accel(pos1, mass)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.accel(pos1, mass, out=acc)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
     st = plan.stats()
-    a = acc.cpu().numpy().astype(np.float64)
-    r = acc_exact.cpu().numpy().astype(np.float64)
-    mag = np.linalg.norm(r, axis=0)
-    e = np.linalg.norm(a - r, axis=0)[mag > 0] / mag[mag > 0]
+    mag = torch.linalg.vector_norm(exact.double(), dim=0)
+    err = torch.linalg.vector_norm(acc.double() - exact.double(), dim=0)
+    keep = mag > 0
+    e = (err[keep] / mag[keep]).cpu().numpy()
+    plan.set_monopole(0.0)
     plan.set_monopole_relative(0.0)
-    return {"alpha": alpha, "ms_per_step": ms, "exact_ms_per_step": exact_step_ms,
-            "speedup": exact_step_ms / ms, "monopole_pairs": int(st["monopoles"]),
+    del acc_ref, pos1, exact, acc
+    return {"theta": theta, "alpha": alpha, "a_ref": "exact FP32 forces one drift step earlier "
+            "(0.02 r_s Gaussian per axis)", "ms_per_step": ms, "exact_ms_per_step": exact_ms,
+            "speedup": exact_ms / ms, "monopole_pairs": int(st["monopoles"]),
             "lane_pairs": int(st["lane_pairs"]) if st["lane_pairs"] >= 0 else None,
             "error_vs_exact": {"particles": int(e.size), "median": nearest_rank(e, 50),
                                "p999": nearest_rank(e, 99.9), "max": float(e.max())}}
@@ -313,11 +343,108 @@ def bench_pm(box, pos, mass, n_mesh, steps, with_error=True):
     return res
 
 
-def bench_batched(steps, warmup, with_error=True):
+def gpu_rel_errors(a, ref):
+    """Nearest-rank median, 99.9th percentile and max of |a - ref| / |ref|
+    over targets with ref != 0, computed on the device."""
+    import torch
+    mag = torch.linalg.vector_norm(ref.double(), dim=0)
+    err = torch.linalg.vector_norm(a.double() - ref.double(), dim=0)
+    keep = mag > 0
+    e = torch.sort(err[keep] / mag[keep]).values
+    n = e.numel()
+    def rank(q):
+        return float(e[max(1, math.ceil(q / 100.0 * n)) - 1]) if n else 0.0
+    return {"targets": int(n), "median": rank(50), "p999": rank(99.9), "max": float(e[-1]) if n else 0.0}
+
+
+def bench_precision(steps=3):
+    """The 16.8M-particle clustered box (L = 400, 8000 spheres): the FP32
+    kernel (FP64 block origins, FP32 pairs, compensated sums) against the
+    FP64 kernel on the same lists: rates, and the FP32 error over all targets
+    taking the FP64 result as the reference."""
+    import torch
+    import workloads
+    import paper_1802_09824_amd as pp
+    box = workloads.make_config(3)
+    n = box.n
+    pos = torch.tensor(box.pos, device="cuda")
+    mass = torch.tensor(box.mass, device="cuda")
+    mass64 = mass.double()
+    box.pos = None                       # the host copy is not needed any more
+    plan = pp.Plan(box.params, n)
+    acc = plan.accel(pos, mass)
+    inter = plan.count_interactions()
+    plan.set_timing(True)
+    k32, t0 = [], time.perf_counter()
+    for _ in range(steps):
+        plan.accel(pos, mass, out=acc)
+        k32.append(plan.stats()["pp_kernel_ms"])
+    torch.cuda.synchronize()
+    step32 = 1e3 * (time.perf_counter() - t0) / steps
+    a64 = plan.accel_f64(pos, mass64)
+    k64 = plan.stats()["pp_kernel_ms"]
+    err = gpu_rel_errors(acc, a64)
+    del plan, pos, mass, mass64, acc, a64
+    torch.cuda.empty_cache()
+    k32m = sum(k32) / len(k32)
+    return {"workload": workloads.CONFIGS[3]["name"], "n": n, "interactions_per_step": inter,
+            "f32": {"ms_per_step": step32, "kernel_ms": k32m, "interactions_per_s_kernel": inter / (k32m * 1e-3),
+                    "interactions_per_s_step": inter / (step32 * 1e-3)},
+            "f64_yardstick": {"kernel_ms": k64, "interactions_per_s_kernel": inter / (k64 * 1e-3)},
+            "f32_error_vs_f64_all_targets": err}
+
+
+def bench_large(steps=2, sample_targets=64):
+    """The largest single-GPU machine: 134M particles in L = 1000, 60 % in 50000
+    Plummer spheres.  Whole-step time, the PP kernel's rate and FP32 peak
+    fraction, the error on a seeded sample of targets against the FP64 CPU
+    oracle, and monopole acceptance (theta = 0.3, alpha = 0.005) one drift
+    step after the reference forces, against the exact path."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    import paper_1802_09824_amd as pp
+    box = workloads.make_config(5)
+    n = box.n
+    pos = torch.tensor(box.pos, device="cuda")
+    mass = torch.tensor(box.mass, device="cuda")
+    plan = pp.Plan(box.params, n)
+    acc = plan.accel(pos, mass)
+    inter = plan.count_interactions()
+    plan.set_timing(True)
+    kms, t0 = [], time.perf_counter()
+    for _ in range(steps):
+        plan.accel(pos, mass, out=acc)
+        kms.append(plan.stats()["pp_kernel_ms"])
+    torch.cuda.synchronize()
+    step = 1e3 * (time.perf_counter() - t0) / steps
+    k = sum(kms) / len(kms)
+    rng = np.random.default_rng(1805)
+    t = np.sort(rng.choice(n, sample_targets, replace=False))
+    ref = oracle.accel(box.pos, box.mass.astype(np.float64), box.params, targets=t)
+    errs = sample_errors(acc[:, torch.as_tensor(t, device="cuda")].cpu().numpy(),
+                         np.arange(t.size), ref)
+    box.pos = None                       # the host copy is not needed any more
+    mono = bench_monopoles(plan, box, pos, mass, steps=1)
+    del plan, pos, mass, acc
+    torch.cuda.empty_cache()
+    achieved = inter * FLOPS_EQUAL_MASS / (k * 1e-3)
+    return {"workload": workloads.CONFIGS[5]["name"], "n": n, "interactions_per_step": inter,
+            "ms_per_step": step, "interactions_per_s": inter / (step * 1e-3),
+            "kernel_ms": k, "interactions_per_s_kernel": inter / (k * 1e-3),
+            "fp32_peak_frac": achieved / FP32_VECTOR_PEAK,
+            "error_vs_oracle_sample": errs, "monopoles": mono}
+
+
+def bench_batched(steps, warmup, with_error=True, tune=True):
     """64 independent boxes (N uniform in 16^3..96^3, L in 50-300 Mpc/h,
     clustered fraction 0-0.8): one batched pp_batch_accel per step (all
     stages over all boxes, one persistent work-stealing PP launch replayed
-    from a hipGraph) against 64 separate pp_accel calls per step."""
+    from a hipGraph) against 64 separate pp_accel calls per step.  Both
+    sides run tiles chosen by the autotuner: the batch its own, every
+    per-box plan its own.  Bit identity with per-box runs is checked at equal
+    tiles (the batch's)."""
     import numpy as np
     import torch
     import workloads
@@ -329,53 +456,67 @@ def bench_batched(steps, warmup, with_error=True):
     N = pos.shape[1]
     acc = torch.empty((3, N), dtype=torch.float32, device="cuda")
     bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    batch_tuning = bp.autotune(pos, mass) if tune else bp.get_tuning()
     bp.accel(pos, mass, out=acc)
     interactions = bp.count_interactions()
     for _ in range(warmup):
         bp.accel(pos, mass, out=acc)
     bp.set_timing(True)
-    graph_ms = []
+    stage_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         bp.accel(pos, mass, out=acc)
-        graph_ms.append(bp.stats()["pp_kernel_ms"])
+        stage_ms.append(bp.stats()["pp_stage_ms"])
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / steps
     acc_batched = acc.cpu().numpy()
     err = batched_error(boxes, acc_batched) if with_error else None
 
-    # per box: separate inputs, plans and launches
+    # per box: separate inputs, plans (each tuned on its own box) and launches
     per = []
+    tunings = {}
     for b in boxes:
         pb = torch.tensor(b.pos, device="cuda")
         mb = torch.tensor(b.mass, device="cuda")
         ab = torch.empty((3, b.n), dtype=torch.float32, device="cuda")
-        per.append((pp.Plan(b.params, b.n), pb, mb, ab))
+        plan = pp.Plan(b.params, b.n)
+        if tune:
+            t = plan.autotune(pb, mb)
+            key = (t["chunk"], t["waves_per_block"], t["persistent"], t["waves_per_cu"])
+            tunings[key] = tunings.get(key, 0) + 1
+        per.append((plan, pb, mb, ab))
     for plan, pb, mb, ab in per:
         plan.accel(pb, mb, out=ab)
         plan.set_timing(True)
-    kernel_ms = 0.0
+    per_stage_ms = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         for plan, pb, mb, ab in per:
             plan.accel(pb, mb, out=ab)
-            kernel_ms += plan.stats()["pp_kernel_ms"]
+            per_stage_ms += plan.stats()["pp_stage_ms"]
     torch.cuda.synchronize()
     t_per = (time.perf_counter() - t0) / steps
-    same = all(np.array_equal(ab.cpu().numpy(), acc_batched[:, o:o + b.n])
-               for (plan, pb, mb, ab), b, o in zip(per, boxes, np.cumsum([0] + [x.n for x in boxes])))
+    # bit identity at equal tiles
+    same = True
+    offs = np.cumsum([0] + [x.n for x in boxes])
+    for (plan, pb, mb, ab), b, o in zip(per, boxes, offs):
+        plan.set_tuning(**{**batch_tuning, "use_graph": 0})
+        plan.accel(pb, mb, out=ab)
+        same = same and np.array_equal(ab.cpu().numpy(), acc_batched[:, o:o + b.n])
     return {
         "workload": "batch-64-boxes-N16^3..96^3-L50-300",
         "boxes": len(boxes), "particles": int(N), "interactions_per_step": interactions,
         "batched": {"ms_per_step": 1e3 * t_batched, "value": interactions / t_batched,
-                    "pp_graph_ms": float(np.mean(graph_ms))},
+                    "pp_stage_ms": float(np.mean(stage_ms)), "tuning": batch_tuning},
         "per_box": {"ms_per_step": 1e3 * t_per, "value": interactions / t_per,
-                    "pp_kernel_ms_sum": kernel_ms / steps},
+                    "pp_stage_ms_sum": per_stage_ms / steps,
+                    "tunings": {f"chunk {k[0]} waves/block {k[1]} persistent {k[2]} waves/CU {k[3]}": v
+                                for k, v in sorted(tunings.items())}},
         "speedup_whole_step": t_per / t_batched,
-        "speedup_pp": (kernel_ms / steps) / float(np.mean(graph_ms)),
-        "bit_identical_to_per_box": bool(same),
+        "speedup_pp_stage": (per_stage_ms / steps) / float(np.mean(stage_ms)),
+        "bit_identical_to_per_box_at_equal_tiles": bool(same),
         "error_vs_oracle": err,
         "unit": "interactions/s",
     }
@@ -407,7 +548,8 @@ def main():
 
     if args.only_batched:
         print(json.dumps({"batched_vs_per_box": bench_batched(max(1, min(args.steps, 5)), 1,
-                                                              with_error=False)}), flush=True)
+                                                              with_error=False,
+                                                              tune=not args.no_tune)}), flush=True)
         return
     box = workloads.make_config(2)
     p = box.params
@@ -415,6 +557,7 @@ def main():
     mass = torch.tensor(box.mass, device="cuda")
     acc = torch.empty((3, box.n), dtype=torch.float32, device="cuda")
     plan = pp.Plan(p, box.n)
+    tuning = plan.get_tuning() if args.no_tune else plan.autotune(pos, mass)   # untimed, one-off
     plan.accel(pos, mass, out=acc)
     interactions = plan.count_interactions()
     for _ in range(args.warmup):
@@ -432,6 +575,8 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     value = interactions * args.steps / elapsed
     k_ms = float(np.mean(kernel_ms))
+    kname = ("pp_f32_persistent" if tuning["persistent"] else "pp_f32_kernel") + \
+        f"<{tuning['variant']}, {tuning['waves_per_block']}>"
     equal_mass = bool(np.all(box.mass == box.mass[0]))
     flops = FLOPS_EQUAL_MASS if equal_mass else FLOPS_GENERAL
     achieved = interactions * flops / (k_ms * 1e-3)
@@ -446,8 +591,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
                      "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
-                     "kernel": "pp_f32_persistent", "kernel_ms": k_ms,
+                     "kernel": kname, "kernel_ms": k_ms,
                      "flops_per_interaction": flops},
+        "tuning": tuning,
         "interactions_per_step": interactions,
         "candidates_per_step": int(st["candidates"]),
         "evaluated_pairs_per_step": int(st["evaluated"]),
@@ -480,14 +626,17 @@ def main():
     out["pm_long_range"] = bench_pm(box, pos, mass, 128, max(3, min(args.steps, 10)),
                                     with_error=not args.no_cpu_baseline)
     if not args.no_extras:
-        plan.accel(pos, mass, out=acc)      # the exact FP32 result as reference
-        out["monopole_relative"] = bench_monopole_relative(plan, pos, mass, acc, ms_step)
+        out["monopoles"] = bench_monopoles(plan, box, pos, mass)
         out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
         out["small_box"] = bench_small_box()
+    del plan, pos, mass, acc
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        out["precision_16.8M"] = bench_precision()
+        out["large_134M"] = bench_large()
     if not args.no_batched:
-        del plan, pos, mass, acc
-        torch.cuda.empty_cache()
-        out["batched_vs_per_box"] = bench_batched(max(1, min(args.steps, 5)), 1)
+        out["batched_vs_per_box"] = bench_batched(max(1, min(args.steps, 5)), 1,
+                                                  tune=not args.no_tune)
     print(json.dumps(out), flush=True)
 
 

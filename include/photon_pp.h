@@ -182,6 +182,8 @@ typedef struct pp_stats {
                                caller's stream) when timing is on, else -1 */
     int64_t monopoles;      /* (target, monopole) pairs of the last pp_accel with
                                monopole acceptance on (0 when off, -1 if unknown) */
+    double pp_stage_ms;     /* the whole PP stage of that call (queue reset, kernel or
+                               graph, reduction, monopoles) when timing is on, else -1 */
 } pp_stats;
 /* Waits for the last PP kernel when timing is on.                          */
 /* Monopole acceptance (sec. 3.3, the 1-to-N case of the dual tree walk) for
@@ -233,25 +235,36 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *               table in LDS (128 quadratic pieces, the form sec. 3.1
  *               describes) instead of the polynomial.  0 is the production
  *               kernel.
- *  groups       reserved, must be 1 (every lane of a wave sweeps every
- *               staged source; sources are pruned against four boxes around
- *               the block's runs of 16 targets before they are staged).
+ *  waves_per_block  1, 2 or 4: waves sharing one work item.  A target block
+ *               (the i tile: up to 64 targets, one per lane) is swept by
+ *               waves_per_block waves, wave k taking the windows k, k + K,
+ *               ... of 64 source-list positions of the item (the j tiles);
+ *               their compensated sums are added in wave order in LDS.  So
+ *               each wave sweeps about chunk / waves_per_block positions per
+ *               item.  More than 1 needs variant 0 or 8.  Every lane of a
+ *               wave sweeps every staged source; sources are pruned against
+ *               four boxes around the block's runs of 16 targets first.
  * The chunk grows by itself when the lists are long enough that more than
- * 2^21 work items would be needed.
+ * 2^21 work items would be needed.  Results are reproducible for a given
+ * tuning; a different chunk or waves_per_block changes the summation order.
  * Defaults: plans {2048, 1, 20, 0, 0, 1}; batch plans {2048, 1, 20, 1, 0, 1}. */
 typedef struct pp_tuning {
-    int32_t chunk, persistent, waves_per_cu, use_graph, variant, groups;
+    int32_t chunk, persistent, waves_per_cu, use_graph, variant, waves_per_block;
 } pp_tuning;
 int pp_plan_get_tuning(const pp_plan* plan, pp_tuning* t);
 int pp_plan_set_tuning(pp_plan* plan, const pp_tuning* t);
 
-/* Autotuner: times the PP stage (HIP events, median of 3 after a warm run)
- * for every chunk in {1024, 2048, 4096, 8192} and launch shape in {one
- * workgroup per item, persistent with 12, 20 or 24 waves per CU} on the
- * given particles, and keeps the fastest in the plan.  With cache_path
- * (may be NULL) the choice is looked up first and stored afterwards, one
- * line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent waves graph groups" per shape
- * class.  The caller's inputs are not modified.  Synchronises the stream.  */
+/* Autotuner: times the PP stage (HIP events around the queue reset, the PP
+ * kernel or its graph and the reduction; median of 3 after a warm run) on
+ * the given particles and keeps the fastest tuning in the plan.  First the
+ * tiles: 1024, 2048 or 4096 source-list positions per wave with 1, 2 or 4
+ * waves per target block (chunk = positions x waves_per_block), persistent
+ * at 20 waves per CU; then, at the best tiles, the launch shape: persistent
+ * with 12, 24 or 32 waves per CU, or one workgroup per item.  The variant is
+ * kept.  With cache_path (may be NULL) the choice is looked up first and
+ * stored afterwards, one line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent
+ * waves graph waves_per_block" per shape class.  The caller's inputs are not
+ * modified.  Synchronises the stream.  */
 int pp_autotune(pp_plan* plan, const double* pos, const float* mass, int64_t n,
                 const char* cache_path, void* stream);
 

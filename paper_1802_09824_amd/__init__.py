@@ -38,7 +38,7 @@ class pp_box_params(C.Structure):
 
 class pp_tuning(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("use_graph", C.c_int32), ("variant", C.c_int32), ("groups", C.c_int32)]
+                ("use_graph", C.c_int32), ("variant", C.c_int32), ("waves_per_block", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -49,7 +49,7 @@ class pp_stats(C.Structure):
                 ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
                 ("evaluated", C.c_int64), ("lane_pairs", C.c_int64),
                 ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double),
-                ("monopoles", C.c_int64)]
+                ("monopoles", C.c_int64), ("pp_stage_ms", C.c_double)]
 
 
 _P, _i64, _i32, _dbl, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_size_t

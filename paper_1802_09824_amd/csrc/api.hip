@@ -60,6 +60,25 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+int HostBuf::reserve(size_t need) {
+    if (need <= bytes) return PP_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, need, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(PP_ENOMEM, "hipHostMalloc failed");
+    }
+    bytes = need;
+    return PP_OK;
+}
+
+HostBuf::~HostBuf() {
+    if (p) (void)hipHostFree(p);
+}
+
 BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
     BoxDev b{};
     b.L = p.L;
@@ -124,7 +143,8 @@ struct Batch {
     pp_stats st{};
     bool lists_valid = false, evaluated_valid = false;
     bool timing = false, timed = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the PP kernel (or its graph)
+    hipEvent_t ev2 = nullptr, ev3 = nullptr;   // around the whole PP stage
     DevBuf partial, pcount, counters, queues;
     // captured PP graph (persistent kernel + reduction)
     hipGraphExec_t gexec = nullptr;
@@ -133,9 +153,8 @@ struct Batch {
     uint64_t graph_gen = 0;
     const void* graph_acc = nullptr;
     const void* graph_active = nullptr;
-    // kernel arguments passed by value: the chunk the items were cut with and
-    // the row stride of the SoA particle arrays
-    int graph_chunk = 0;
+    // the row stride of the SoA particle arrays, a kernel argument passed by
+    // value (the chunk and the counts are read on the device)
     int64_t graph_n = -1;
 
     ~Batch() {
@@ -143,6 +162,8 @@ struct Batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (ev2) (void)hipEventDestroy(ev2);
+        if (ev3) (void)hipEventDestroy(ev3);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 
@@ -186,18 +207,21 @@ struct Batch {
         PP_TRY(w.pos_s.reserve(24 * m));
         PP_TRY(w.mass_s.reserve(4 * m));
         PP_TRY(w.bad.reserve(64));
+        PP_TRY(w.misc.reserve(64));
         PP_TRY(counters.reserve(64));
         PP_TRY(queues.reserve(64));
         return PP_OK;
     }
 
     // Stages shared by every entry point: keys, sort, gather, leaves, trees,
-    // block lists.  Synchronises the stream.
+    // block lists.  Nothing is read back: the counts stay on the device until
+    // finish() (see lists_to_host).
     int prepare(const double* pos, const float* mass_f, const double* mass_d, hipStream_t s,
                 const uint8_t* active = nullptr) {
         lists_valid = false;
         evaluated_valid = false;
         w.pos_n = N;
+        PP_TRY(reset_sizes(w, s));
         PP_HIP(hipMemsetAsync(w.bad.p, 0, sizeof(int), s));
         PP_TRY(stage_keys(bd, N, pos, w, s));
         PP_TRY(stage_sort(bd, N, w, s));
@@ -208,11 +232,8 @@ struct Batch {
             PP_TRY(launch_split_table(w, s));
             table_ready = true;
         }
-        int bad = 0;
-        PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s,
-                            w.bad.as<int>(), &bad));
-        if (bad) return fail(PP_EINVAL, "non-finite position or mass");
-        PP_TRY(stage_trees(bd, w, s));
+        PP_TRY(stage_leaves(bd, N, w.keys_s.as<uint64_t>(), w.pos_s.as<double>(), w, s));
+        PP_TRY(stage_trees(bd, N, w, s));
         // monopoles only on the FP32 path: the FP64 yardstick and the pair
         // count keep exact lists
         MonoCfg mc;
@@ -225,12 +246,24 @@ struct Batch {
         if (mono && mc.alpha > 0.0 && acc_ref_n != N)
             return fail(PP_EINVAL, "the reference accelerations were given for another particle count");
         if (mono) {
-            PP_TRY(stage_node_moments(bd, w, s));
+            PP_TRY(stage_node_moments(bd, N, w, s));
             mc.mc = w.tree_mc.as<double4>();
         }
         PP_TRY(stage_lists(bd, poff, tune.chunk, w, s, mc, active));
         lists_mono = mono;
         lists_active = active != nullptr;
+        return PP_OK;
+    }
+
+    // The end of a pass: reads the counts back (one synchronisation).  With
+    // *again set, a buffer was too small (the PP kernels did nothing) and the
+    // pass must run again with the grown capacities.
+    int finish(hipStream_t s, bool* again) {
+        PP_TRY(lists_to_host(w, s, again));
+        if (*again) {
+            evaluated_valid = false;
+            return PP_OK;
+        }
         st.n = N;
         st.nleaf = w.nleaf;
         st.nblock = w.nblock;
@@ -238,11 +271,23 @@ struct Batch {
         st.nitem = w.nitem;
         st.candidates = w.candidates;
         st.interactions = -1;
-        st.evaluated = -1;
-        st.lane_pairs = -1;
         st.pp_kernel_ms = -1.0;
         lists_valid = true;
         return PP_OK;
+    }
+
+    // The FP32 short-range accelerations: prepare, PP, finish, repeated
+    // while a buffer had to grow.
+    int accel_f32(const double* pos, const float* mass, float* acc, hipStream_t s,
+                  const uint8_t* active = nullptr) {
+        for (int attempt = 0; attempt < 32; ++attempt) {
+            PP_TRY(prepare(pos, mass, nullptr, s, active));
+            PP_TRY(run_f32(acc, s));
+            bool again = false;
+            PP_TRY(finish(s, &again));
+            if (!again) return PP_OK;
+        }
+        return fail(PP_ENOMEM, "the list buffers kept growing");
     }
 
     int run_pp_direct(float* acc, hipStream_t s) {
@@ -250,7 +295,7 @@ struct Batch {
         PP_HIP(hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s));
         if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
         if (timing) PP_HIP(hipEventRecord(ev0, s));
-        PP_TRY(launch_pp_f32(bd, w, tune.groups, tune.persistent ? Mode::kPersistent : Mode::kGrid,
+        PP_TRY(launch_pp_f32(bd, w, tune.waves_per_block, tune.persistent ? Mode::kPersistent : Mode::kGrid,
                              tune.waves_per_cu, tune.variant, partial.as<float>(), acc, ctr,
                              queues.as<unsigned>(), s));
         if (timing) {
@@ -279,7 +324,7 @@ struct Batch {
         PP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = launch_reset_queues(queues.as<unsigned>(), s);
         if (rc == PP_OK)
-            rc = launch_pp_f32(bd, w, tune.groups, Mode::kPersistent, tune.waves_per_cu, tune.variant,
+            rc = launch_pp_f32(bd, w, tune.waves_per_block, Mode::kPersistent, tune.waves_per_cu, tune.variant,
                                partial.as<float>(), acc, nullptr, queues.as<unsigned>(), s);
         if (rc == PP_OK) rc = launch_reduce_f32(bd, w, partial.as<float>(), acc, s);
         hipError_t e = hipStreamEndCapture(s, &graph);
@@ -289,23 +334,30 @@ struct Batch {
         graph_gen = alloc_generation();
         graph_acc = acc;
         graph_active = w.active;
-        graph_chunk = w.chunk;
         graph_n = w.pos_n;
         graph_variant = graph_key();
         return PP_OK;
     }
 
-    // what the captured launch depends on besides buffers: variant, groups, waves
+    // what the captured launch depends on besides buffers: variant, waves per block and per CU
     int64_t graph_key() const {
-        return ((int64_t)tune.variant << 32) | ((int64_t)tune.groups << 16) | (int64_t)tune.waves_per_cu;
+        return ((int64_t)tune.variant << 32) | ((int64_t)tune.waves_per_block << 16) | (int64_t)tune.waves_per_cu;
     }
 
+    // The PP stage: queue reset, PP kernel (or its graph), reduction and
+    // monopoles; with timing on, events around the stage and the kernel.
     int run_f32(float* acc, hipStream_t s) {
-        PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.nitem + 1)));
+        PP_TRY(partial.reserve(sizeof(float) * 3 * kBlock * (w.cap_item + 1)));
+        if (timing) PP_HIP(hipEventRecord(ev2, s));
+        PP_TRY(run_f32_stage(acc, s));
+        if (timing) PP_HIP(hipEventRecord(ev3, s));
+        return PP_OK;
+    }
+
+    int run_f32_stage(float* acc, hipStream_t s) {
         if (tune.persistent && tune.use_graph) {
             if (!gexec || graph_gen != alloc_generation() || graph_acc != acc ||
-                graph_active != w.active || graph_variant != graph_key() ||
-                graph_chunk != w.chunk || graph_n != w.pos_n)
+                graph_active != w.active || graph_variant != graph_key() || graph_n != w.pos_n)
                 PP_TRY(capture(acc));
             if (timing) PP_HIP(hipEventRecord(ev0, s));
             PP_HIP(hipGraphLaunch(gexec, s));
@@ -322,11 +374,14 @@ struct Batch {
 
     int stats(pp_stats* out) {
         st.pp_kernel_ms = -1.0;
+        st.pp_stage_ms = -1.0;
         if (timing && timed) {
-            PP_HIP(hipEventSynchronize(ev1));
+            PP_HIP(hipEventSynchronize(ev3));
             float ms = 0.f;
             PP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
             st.pp_kernel_ms = ms;
+            PP_HIP(hipEventElapsedTime(&ms, ev2, ev3));
+            st.pp_stage_ms = ms;
         }
         st.evaluated = st.lane_pairs = -1;
         st.monopoles = lists_mono ? -1 : 0;
@@ -341,25 +396,37 @@ struct Batch {
         return PP_OK;
     }
 
-    // Time the PP stage (events around kernel or graph) for the current
-    // tuning: median of `reps` runs after one warm run.
+    // Time the PP stage for the current tuning: events of its own around
+    // everything run_f32 enqueues (queue reset, PP kernel or graph,
+    // reduction), the same span for every launch shape; median of `reps`
+    // runs after one warm run.
     int time_pp(const double* pos, const float* mass, float* acc, int reps, hipStream_t s,
                 float* ms_out) {
-        const bool was = timing;
-        PP_TRY(set_timing(1));
-        PP_TRY(prepare(pos, mass, nullptr, s));
-        PP_TRY(run_f32(acc, s));
+        PP_TRY(accel_f32(pos, mass, acc, s));
+        hipEvent_t a = nullptr, b = nullptr;
+        PP_HIP(hipEventCreate(&a));
+        hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return hip_fail(e, "hipEventCreate", __FILE__, __LINE__);
+        }
         std::vector<float> t;
-        for (int r = 0; r < reps; ++r) {
-            PP_TRY(run_f32(acc, s));
-            PP_HIP(hipEventSynchronize(ev1));
+        int rc = PP_OK;
+        for (int r = 0; r < reps && rc == PP_OK; ++r) {
+            e = hipEventRecord(a, s);
+            if (e == hipSuccess) rc = run_f32(acc, s);
+            if (rc == PP_OK && e == hipSuccess) e = hipEventRecord(b, s);
+            if (rc == PP_OK && e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0.f;
-            PP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            if (rc == PP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess && rc == PP_OK) rc = hip_fail(e, "PP timing events", __FILE__, __LINE__);
             t.push_back(ms);
         }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        PP_TRY(rc);
         std::sort(t.begin(), t.end());
         *ms_out = t[t.size() / 2];
-        timing = was;
         return PP_OK;
     }
 
@@ -390,7 +457,7 @@ struct Batch {
                 std::string k;
                 pp_tuning t{};
                 t.variant = tune.variant;
-                if (ls >> k >> t.chunk >> t.persistent >> t.waves_per_cu >> t.use_graph >> t.groups &&
+                if (ls >> k >> t.chunk >> t.persistent >> t.waves_per_cu >> t.use_graph >> t.waves_per_block &&
                     k == key &&
                     check_tuning_ok(t)) {
                     tune = t;
@@ -400,24 +467,36 @@ struct Batch {
             }
         }
         const bool batch = nbox > 1;
-        const int chunks[] = {1024, 2048, 4096, 8192};
-        struct Shape { int persistent, waves; };
-        const Shape shapes[] = {{0, 24}, {1, 12}, {1, 20}, {1, 24}};
+        const int variant = tune.variant;
+        const bool multi = variant == 0 || variant == 8;      // K > 1 is built for these
         pp_tuning best = tune;
         float best_ms = 1e30f;
-        for (int c : chunks) {
-            for (const Shape& sh : shapes) {
-                pp_tuning t{c, sh.persistent, sh.waves, sh.persistent && batch ? 1 : 0, tune.variant,
-                            tune.groups};
-                tune = t;
-                float ms = 0.f;
-                PP_TRY(time_pp(pos, mass, acc, 3, s, &ms));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
-                }
+        auto trial = [&](const pp_tuning& t) -> int {
+            tune = t;
+            float ms = 0.f;
+            PP_TRY(time_pp(pos, mass, acc, 3, s, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
             }
-        }
+            return PP_OK;
+        };
+        // 1) the j tile: source-list positions per wave, and K waves per
+        //    target block (a block's i tile of 64 targets swept by K waves),
+        //    persistent at 20 waves per CU
+        const int chunks[] = {1024, 2048, 4096};
+        const int ks[] = {1, 2, 4};
+        for (int c : chunks)
+            for (int k : ks) {
+                if (k > 1 && !multi) continue;
+                PP_TRY(trial(pp_tuning{c * k, 1, 20, batch ? 1 : 0, variant, k}));
+            }
+        // 2) the launch shape at that tiling: resident waves per CU, or one
+        //    workgroup per item
+        const pp_tuning tiled = best;
+        for (int wpc : {12, 24, 32})
+            PP_TRY(trial(pp_tuning{tiled.chunk, 1, wpc, batch ? 1 : 0, variant, tiled.waves_per_block}));
+        PP_TRY(trial(pp_tuning{tiled.chunk, 0, 20, 0, variant, tiled.waves_per_block}));
         tune = best;
         lists_valid = false;
         if (cache_path) {
@@ -432,7 +511,7 @@ struct Batch {
             if (!out) return fail(PP_EINVAL, std::string("cannot write tuning cache ") + cache_path);
             for (const std::string& l : keep) out << l << "\n";
             out << key << " " << best.chunk << " " << best.persistent << " " << best.waves_per_cu
-                << " " << best.use_graph << " " << best.groups << "\n";
+                << " " << best.use_graph << " " << best.waves_per_block << "\n";
         }
         return PP_OK;
     }
@@ -440,13 +519,17 @@ struct Batch {
     static bool check_tuning_ok(const pp_tuning& t) {
         return t.chunk >= 64 && t.chunk <= (1 << 24) && t.chunk % 64 == 0 && t.waves_per_cu >= 1 &&
                t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
-               t.variant <= 15 && t.groups == 1;
+               t.variant <= 15 &&
+               (t.waves_per_block == 1 ||
+                ((t.waves_per_block == 2 || t.waves_per_block == 4) && (t.variant == 0 || t.variant == 8)));
     }
 
     int set_timing(int on) {
         if (on && !ev0) {
             PP_HIP(hipEventCreate(&ev0));
             PP_HIP(hipEventCreate(&ev1));
+            PP_HIP(hipEventCreate(&ev2));
+            PP_HIP(hipEventCreate(&ev3));
         }
         timing = on != 0;
         timed = false;
@@ -461,7 +544,10 @@ static int check_tuning(const pp_tuning* t) {
     if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
     if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
     if (t->variant < 0 || t->variant > 15) return fail(PP_EINVAL, "variant must be in 0..15");
-    if (t->groups != 1) return fail(PP_EINVAL, "groups must be 1");
+    if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
+        return fail(PP_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (t->waves_per_block > 1 && t->variant != 0 && t->variant != 8)
+        return fail(PP_EINVAL, "more than one wave per block needs variant 0 or 8");
     return PP_OK;
 }
 
@@ -584,10 +670,7 @@ int pp_build_leaves(const uint64_t* sorted_keys, const double* pos_sorted, int64
         rc = stage_wrap_copy(lv->b.bd, n, pos_sorted, lv->b.w.pos_s.as<double>(), S(stream));
     if (rc == PP_OK)
         rc = stage_leaves(lv->b.bd, n, sorted_keys, lv->b.w.pos_s.as<double>(), lv->b.w, S(stream));
-    if (rc == PP_OK) {
-        hipError_t e = hipStreamSynchronize(S(stream));
-        if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
-    }
+    if (rc == PP_OK) rc = leaves_to_host(lv->b.bd, lv->b.w, S(stream));
     if (rc != PP_OK) {
         delete lv;
         return rc;
@@ -614,7 +697,7 @@ int pp_leaves_export(const pp_leaves* lv, int64_t* begin, int32_t* count, int32_
     if (prefix) PP_HIP(hipMemcpy(prefix, w.lprefix.p, 8 * m, hipMemcpyDefault));
     if (lo || hi) {
         std::vector<IBox> hb(m);
-        PP_HIP(hipMemcpy(hb.data(), w.lboxes.p, sizeof(IBox) * m, hipMemcpyDeviceToHost));
+        PP_HIP(hipMemcpy(hb.data(), w.tree_boxes.p, sizeof(IBox) * m, hipMemcpyDeviceToHost));
         std::vector<int32_t> t(3 * m);
         for (int k = 0; k < 2; ++k) {
             int32_t* dst = k == 0 ? lo : hi;
@@ -640,7 +723,8 @@ int pp_near_pairs(pp_leaves* lv, const pp_box_params* p, pp_pairs** out, void* s
     pp_pairs* pr = new (std::nothrow) pp_pairs;
     if (!pr) return fail(PP_ENOMEM, "host allocation failed");
     const BoxDev g = make_boxdev(*p, 0, lv->b.N);
-    int rc = stage_trees(lv->b.bd, lv->b.w, S(stream));
+    int rc = stage_trees(lv->b.bd, lv->b.N, lv->b.w, S(stream));
+    if (rc == PP_OK) rc = trees_to_host(lv->b.bd, lv->b.w, S(stream));
     if (rc == PP_OK)
         rc = build_canonical_pairs(lv->b.bd, lv->b.w, g.W, g.T, pr->row_cnt, pr->row_ptr, pr->src,
                                    pr->code, pr->scan_ws, &pr->nentries, S(stream));
@@ -723,9 +807,7 @@ int pp_accel(pp_plan* pl, const double* pos, const float* mass, int64_t n, float
     PP_TRY(check_accel_args(pl, pos, mass, n, acc));
     if (n == 0) return PP_OK;
     PP_TRY(plan_resize(pl, n));
-    hipStream_t s = S(stream);
-    PP_TRY(pl->b.prepare(pos, mass, nullptr, s));
-    return pl->b.run_f32(acc, s);
+    return pl->b.accel_f32(pos, mass, acc, S(stream));
 }
 
 int pp_accel_active(pp_plan* pl, const double* pos, const float* mass, int64_t n,
@@ -734,9 +816,7 @@ int pp_accel_active(pp_plan* pl, const double* pos, const float* mass, int64_t n
     PP_TRY(check_ptr(active, n, "active"));
     if (n == 0) return PP_OK;
     PP_TRY(plan_resize(pl, n));
-    hipStream_t s = S(stream);
-    PP_TRY(pl->b.prepare(pos, mass, nullptr, s, active));
-    return pl->b.run_f32(acc, s);
+    return pl->b.accel_f32(pos, mass, acc, S(stream), active);
 }
 
 int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, double* acc,
@@ -746,16 +826,23 @@ int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, 
     PP_TRY(plan_resize(pl, n));
     hipStream_t s = S(stream);
     Batch& b = pl->b;
-    PP_TRY(b.prepare(pos, nullptr, mass, s));
-    PP_TRY(b.partial.reserve(sizeof(double) * 3 * kBlock * (b.w.nitem + 1)));
-    if (b.timing) PP_HIP(hipEventRecord(b.ev0, s));
-    PP_TRY(launch_pp_f64(b.bd, b.w, b.w.chunk, reinterpret_cast<double*>(b.partial.p), s));
-    if (b.timing) {
-        PP_HIP(hipEventRecord(b.ev1, s));
-        b.timed = true;
+    for (int attempt = 0; attempt < 32; ++attempt) {
+        PP_TRY(b.prepare(pos, nullptr, mass, s));
+        PP_TRY(b.partial.reserve(sizeof(double) * 3 * kBlock * (b.w.cap_item + 1)));
+        if (b.timing) PP_HIP(hipEventRecord(b.ev2, s));
+        if (b.timing) PP_HIP(hipEventRecord(b.ev0, s));
+        PP_TRY(launch_pp_f64(b.bd, b.w, reinterpret_cast<double*>(b.partial.p), s));
+        if (b.timing) {
+            PP_HIP(hipEventRecord(b.ev1, s));
+            b.timed = true;
+        }
+        PP_TRY(launch_reduce_f64(b.bd, b.w, reinterpret_cast<double*>(b.partial.p), acc, s));
+        if (b.timing) PP_HIP(hipEventRecord(b.ev3, s));
+        bool again = false;
+        PP_TRY(b.finish(s, &again));
+        if (!again) return PP_OK;
     }
-    PP_TRY(launch_reduce_f64(b.bd, b.w, reinterpret_cast<double*>(b.partial.p), acc, s));
-    return PP_OK;
+    return fail(PP_ENOMEM, "the list buffers kept growing");
 }
 
 int pp_plan_set_monopole(pp_plan* pl, double theta) {
@@ -857,8 +944,8 @@ static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStre
         return fail(PP_EINVAL, "the lists hold monopoles: count after pp_accel_f64 or with theta 0");
     if (b.lists_active)
         return fail(PP_EINVAL, "the lists cover the active targets only: count after pp_accel or pp_accel_f64");
-    PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.nitem + 1)));
-    PP_TRY(launch_count(b.bd, b.w, b.w.chunk, b.pcount.as<int32_t>(), s));
+    PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.cap_item + 1)));
+    PP_TRY(launch_count(b.bd, b.w, b.pcount.as<int32_t>(), s));
     unsigned long long* tot = b.w.misc.as<unsigned long long>() + 4;
     PP_HIP(hipMemsetAsync(tot, 0, sizeof(unsigned long long), s));
     PP_TRY(launch_reduce_count(b.bd, b.w, b.pcount.as<int32_t>(), counts, tot, s));
@@ -917,9 +1004,7 @@ int pp_batch_accel(pp_batch_plan* bp, const double* pos, const float* mass, floa
     PP_TRY(check_ptr(mass, b.N, "mass"));
     PP_TRY(check_ptr(acc, b.N, "acc"));
     if (b.N == 0) return PP_OK;
-    hipStream_t s = S(stream);
-    PP_TRY(b.prepare(pos, mass, nullptr, s));
-    return b.run_f32(acc, s);
+    return b.accel_f32(pos, mass, acc, S(stream));
 }
 
 int pp_batch_count_interactions(pp_batch_plan* bp, int64_t* counts, int64_t* total, void* stream) {

@@ -142,8 +142,59 @@ struct FEntry {
     uint8_t mono;    // taken as a monopole (monopole acceptance on)
 };
 
+// Slots of Work::sizes (int64, device).  The list builder writes the counts
+// of the current lists here and every later kernel reads them, so that no
+// count has to come back to the host before the pass's last kernel.  Counts
+// are clamped to the capacities the buffers were sized with; the kNeed
+// slots keep the totals, from which the host grows the buffers when one was
+// too small (and then runs the pass again).
+enum SizeSlot : int {
+    kNBlock = 0,        // target blocks
+    kNItem = 1,         // work items
+    kNRange = 2,        // source ranges
+    kNEntry = 3,        // final entries of the list expansion
+    kNLeaf = 4,         // leaves
+    kTotalSrc = 5,      // listed sources summed over the blocks
+    kChunk = 6,         // source-list positions per work item (the effective chunk)
+    kSkip = 7,          // nonzero: a buffer was too small or an input not finite; the PP kernels return
+    kCand = 8,          // (target, listed source) pairs
+    kOverflow = 9,      // bit 0: blocks, 1: entries, 2: ranges, 3: items, 4: a list longer than int32
+    kBad = 10,          // a non-finite position or mass
+    kNeedBlock = 11,
+    kNeedRange = 12,
+    kNeedItem = 13,
+    kEntry0 = 16,       // kEntry0 + p: entries after expansion pass p (clamped)
+    kNeedEntry0 = 40,   // kNeedEntry0 + p: the same, unclamped
+    kSizeSlots = 64
+};
+constexpr int kMaxPasses = kTreeMaxLevels + 1;
+constexpr int64_t kEntryBudget = (int64_t)1 << 28;
+
+// Page-locked host buffer (hipHostMalloc) for the counts read back at the
+// end of a pass.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int reserve(size_t need);
+    template <class T> T* as() const { return static_cast<T*>(p); }
+    ~HostBuf();
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+};
+
 struct Work {
     int64_t pos_n = 0;       // particles in the current batch (row stride of pos_s)
+    // capacities the list buffers are sized with (grown when a pass reports
+    // a larger need); entries per expansion pass
+    int64_t cap_block = 0, cap_range = 0, cap_item = 0;
+    int64_t cap_ent[kMaxPasses] = {};
+    int npass = 0;                        // expansion passes of the current lists
+    // the last pass lowers the entries from level 2 to level 1 unless that
+    // would need more than kEntryBudget entries; then the depth-first walks
+    // start at level 2 (64 leaves each) for the rest of the plan's life
+    bool stop_at_level2 = false;
+    HostBuf sizes_h;                      // host copy of sizes after a pass
     // particles
     DevBuf keys, keys_s, iota, perm, pos_s, mass_s, mass_sd, bad;
     DevBuf rec;              // double4 [N]: wrapped position and mass, input order (gather staging)
@@ -159,28 +210,28 @@ struct Work {
     const uint64_t* mono0 = nullptr;
     const uint8_t* mono1 = nullptr;
     const uint8_t* active = nullptr;     // the items' target flags (null: every target)
-    std::vector<int64_t> lvl_prefix_host;
     DevBuf sort_ws, scan_ws, sort_tmp;
     // leaves
     DevBuf lam, pmax, smax, level_p, flag, flag_off;
-    DevBuf lbegin, lcount, llevel, lprefix, lboxes, loff_dev;
-    int64_t nleaf = 0;
-    std::vector<int64_t> loff;            // host copy [nbox + 1]
+    DevBuf lbegin, lcount, llevel, lprefix, loff_dev;   // leaf boxes: tree_boxes[0 .. nleaf)
+    int64_t nleaf = 0;                    // host copies, valid after leaves_to_host
+    std::vector<int64_t> loff;            //   or lists_to_host ([nbox + 1])
     // trees
-    DevBuf tree_boxes, tviews, lvl_prefix;
-    std::vector<TreeView> tv;             // host copy [nbox]
-    int max_levels = 0;
-    // blocks, lists, items
+    DevBuf tree_boxes, tviews, lvl_prefix, tree_total;
+    std::vector<TreeView> tv;             // host copy [nbox], valid after trees_to_host
+    int max_levels = 0;                   // bound on the tree levels of any box
+    // blocks, lists, items (host copies, valid after lists_to_host)
     int64_t nchunk = 0, nblock = 0, nentry = 0, nrange = 0, nitem = 0;
     int64_t candidates = 0;
     int chunk = 0;           // effective chunk of the current items (>= the requested one)
+    std::vector<int64_t> choff_h;         // chunk offsets of the boxes (host)
     DevBuf choff, ccount, coff;
     DevBuf bstart, bcount, bbox, bboxid;
     DevBuf fent_a, fent_b, fcnt, foff;
     DevBuf lmask_e, rcnt_e, scnt_e, roff_e, soff_e, eoff;
     DevBuf roff, slen, rbeg, rpre, rcode;
     DevBuf icount, ioff, iblock, is0;
-    DevBuf sizes;      // int64 [8]: nblock, nitem, ... read by graph-captured kernels
+    DevBuf sizes;      // int64 [kSizeSlots], see SizeSlot
     DevBuf misc;       // counters and flags
 };
 
@@ -206,11 +257,17 @@ int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_
                     hipStream_t s);
 
 // tree.hip  (positions passed here are wrapped: x - L floor(x / L))
-// Leaves of every box.  Synchronises the stream once; when bad_dev is given
-// the int it points to is read back into *bad_host in the same transfer.
+// These stages keep their counts on the device (Work::sizes, the leaf and
+// tree offsets); nothing is read back until the *_to_host calls.
+// Leaves of every box (buffers sized for N leaves).
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
-                 Work& w, hipStream_t s, const int* bad_dev = nullptr, int* bad_host = nullptr);
-int stage_trees(const BatchDev& bd, Work& w, hipStream_t s);
+                 Work& w, hipStream_t s);
+// w.loff and w.nleaf from the device.  Synchronises the stream.
+int leaves_to_host(const BatchDev& bd, Work& w, hipStream_t s);
+// The implicit 8-ary trees over every box's leaves (levels bounded from N).
+int stage_trees(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
+// w.tv from the device.  Synchronises the stream.
+int trees_to_host(const BatchDev& bd, Work& w, hipStream_t s);
 // Monopole acceptance settings of the list expansion (nodes of level >= 2):
 // every enabled test must hold.  theta2 = theta^2 of the geometric test
 // (0: off); alpha of Gadget-2's relative test against reference
@@ -223,13 +280,22 @@ struct MonoCfg {
     const float* acc_ref = nullptr;
     bool on() const { return theta2 > 0.0 || alpha > 0.0; }
 };
+// Target blocks, near lists and work items, counts on the device; buffers
+// sized with the capacities in w (see lists_to_host).
 // active: optional device flags per input particle; target blocks without an
 // active target get no work items (their outputs are left alone).
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
                 hipStream_t s, const MonoCfg& mono = MonoCfg(), const uint8_t* active = nullptr);
+// Zero the count slots at the start of a pass.
+int reset_sizes(Work& w, hipStream_t s);
+// Reads the counts of the last pass back (synchronises the stream).  Sets
+// *regrow and grows the capacities when a buffer was too small (the pass must
+// then run again); PP_EINVAL when an input was not finite.  Otherwise fills
+// the host copies (nleaf, nblock, nentry, nrange, nitem, candidates, chunk).
+int lists_to_host(Work& w, hipStream_t s, bool* regrow);
 // Mass and mass-weighted position sums of every tree node (after stage_trees;
 // needs the FP32 masses in key order).
-int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s);
+int stage_node_moments(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
 // Adds the monopoles' forces to acc (input order), FP32 path.
 int launch_monopole(const BatchDev& bd, const Work& w, float* acc, unsigned long long* counter,
                     hipStream_t s);
@@ -248,10 +314,10 @@ int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int 
                   unsigned* queues, hipStream_t s);
 int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,
                       hipStream_t s);
-int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial, hipStream_t s);
+int launch_pp_f64(const BatchDev& bd, const Work& w, double* partial, hipStream_t s);
 int launch_reduce_f64(const BatchDev& bd, const Work& w, const double* partial, double* acc,
                       hipStream_t s);
-int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial, hipStream_t s);
+int launch_count(const BatchDev& bd, const Work& w, int32_t* partial, hipStream_t s);
 int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partial, int64_t* counts,
                         unsigned long long* total, hipStream_t s);
 // Builds the interpolated split table (FP64 series, rounded to FP32).

@@ -33,7 +33,7 @@ namespace {
 struct ItemArgs {
     const int32_t* iblock;
     const int32_t* is0;
-    const int64_t* sizes;      // [0] nblock, [1] nitem
+    const int64_t* sizes;      // the counts of the lists (SizeSlot), on the device
     const int32_t* bstart;
     const int32_t* bcount;
     const IBox* bbox;
@@ -50,14 +50,13 @@ struct ItemArgs {
     const float4* split_tab;   // the interpolated split table (variant bit 8)
     float* acc;                // FP32 output (single-item blocks write it directly)
     const uint8_t* active;     // per input particle: outputs written only where set (null: all)
-    int chunk;
 };
 
 __device__ __forceinline__ bool target_on(const ItemArgs& ia, int64_t i) {
     return !ia.active || ia.active[i] != 0;
 }
 
-ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
+ItemArgs item_args(const BatchDev& bd, const Work& w) {
     ItemArgs ia;
     ia.iblock = w.iblock.as<int32_t>();
     ia.is0 = w.is0.as<int32_t>();
@@ -78,7 +77,6 @@ ItemArgs item_args(const BatchDev& bd, const Work& w, int /*chunk*/) {
     ia.split_tab = w.split_tab.as<float4>();
     ia.acc = nullptr;
     ia.active = w.active;
-    ia.chunk = w.chunk;       // the effective chunk the items were cut with
     return ia;
 }
 
@@ -224,22 +222,33 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 // around the block's runs of 16 targets.  Survivors are compacted with a
 // ballot into a 128-entry LDS ring; every 64 survivors are swept by all
 // lanes with broadcast LDS reads.
-template <int VAR>
+//
+// K waves may share one item (the workgroup is K waves): wave k takes the
+// windows k, k + K, k + 2K, ... of the item's list, stages and sweeps them
+// into its own LDS ring and its own compensated sums, and the K sums are
+// added in wave order in FP64 (through LDS) before the item's result is
+// written.  The split does not depend on scheduling, so results stay
+// reproducible for a given K.
+template <int VAR, int K>
 __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
                                         const double* __restrict__ pos_s,
                                         const float* __restrict__ mass_s, int64_t N,
                                         float* __restrict__ partial,
-                                        unsigned long long* __restrict__ counters, float4* tile,
-                                        const float4* __restrict__ tab) {
+                                        unsigned long long* __restrict__ counters, float4* tile_all,
+                                        const float4* __restrict__ tab, float4* qb_all,
+                                        double* red) {
     constexpr bool NEWTON = (VAR & 1) != 0;
     constexpr bool KAHAN = (VAR & 2) == 0;
     constexpr bool LOCAL = (VAR & 4) == 0;     // FP64 block-centre subtraction
     constexpr bool TABLE = (VAR & 8) != 0;     // interpolated split table
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kBlock - 1);
+    const int wv = K > 1 ? (int)(threadIdx.x / kBlock) : 0;
+    float4* tile = tile_all + wv * 2 * kBlock;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
-    const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
+    const int32_t chunk = (int32_t)ia.sizes[kChunk];
+    const int32_t s1 = s0 + chunk < S ? s0 + chunk : S;
     const int32_t nt = ia.bcount[b];
     const int xbox = ia.bboxid[b];
     const BoxDev& X = ia.box[xbox];
@@ -271,7 +280,7 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     // that pass the whole block's box.  Widened like the block box.
     constexpr int GROUPS = 4;
     constexpr int GW = kBlock / GROUPS;
-    __shared__ float4 qb[2 * GROUPS];
+    float4* qb = qb_all + wv * 2 * GROUPS;
     if (LOCAL) {
         float ax_ = lane < nt ? xi : INFINITY, bx_ = lane < nt ? xi : -INFINITY;
         float ay_ = lane < nt ? yi : INFINITY, by_ = lane < nt ? yi : -INFINITY;
@@ -311,7 +320,8 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     int count = 0;                                   // staged sources (wave-uniform)
     int64_t staged = 0;
-    int64_t rcur = s1 > s0 ? find_range(ia.rpre, r_lo, r_hi, s0) : r_lo;
+    const int32_t first = s0 + wv * kBlock;          // this wave's first window
+    int64_t rcur = s1 > first ? find_range(ia.rpre, r_lo, r_hi, first) : r_lo;
 
     double px = 0, py = 0, pz = 0;
     float pm = 0.f;
@@ -323,7 +333,8 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         int64_t r = rcur;
         const int32_t end_cur = rcur < r_hi ? ia.rpre[rcur + 1] : S;
         if (base + kBlock > end_cur) {
-            const int64_t top = rcur + kBlock < r_hi ? rcur + kBlock : r_hi;
+            // the window starts at most K * 64 positions (so ranges) past the cursor's
+            const int64_t top = rcur + K * kBlock < r_hi ? rcur + K * kBlock : r_hi;
             if (pv) r = find_range(ia.rpre, rcur, top, p);
         }
         if (pv) {
@@ -337,8 +348,8 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         rcur = readlane64(r, kBlock - 1);
     };
     wave_sync();
-    if (s0 < s1) fetch(s0);
-    for (int32_t base = s0; base < s1; base += kBlock) {
+    if (first < s1) fetch(first);
+    for (int32_t base = first; base < s1; base += K * kBlock) {
         bool keep = false;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (pv) {
@@ -378,7 +389,7 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         count += got;
         staged += got;
         // the next window's loads stay in flight while this tile is swept
-        if (base + kBlock < s1) fetch(base + kBlock);
+        if (base + K * kBlock < s1) fetch(base + K * kBlock);
         if (count >= kBlock) {
             wave_sync();
             float tx = 0.f, ty = 0.f, tz = 0.f;
@@ -424,22 +435,41 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         atomicAdd(counters, (unsigned long long)staged * (unsigned long long)nt);
         atomicAdd(counters + 1, (unsigned long long)staged * (unsigned long long)kBlock);
     }
+    // the compensated sums, then (K > 1) the waves' sums in wave order
+    double sx = (double)ax - (double)cx, sy = (double)ay - (double)cy, sz = (double)az - (double)cz;
+    if (K > 1) {
+        __syncthreads();                 // every wave is done with the previous item's sums
+        red[(wv * 3 + 0) * kBlock + lane] = sx;
+        red[(wv * 3 + 1) * kBlock + lane] = sy;
+        red[(wv * 3 + 2) * kBlock + lane] = sz;
+        __syncthreads();
+        if (wv != 0) return;
+        sx = red[0 * kBlock + lane];
+        sy = red[1 * kBlock + lane];
+        sz = red[2 * kBlock + lane];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            sx += red[(k * 3 + 0) * kBlock + lane];
+            sy += red[(k * 3 + 1) * kBlock + lane];
+            sz += red[(k * 3 + 2) * kBlock + lane];
+        }
+    }
     if (ia.acc && ia.ioff[b + 1] - ia.ioff[b] == 1) {
         // the block's only item: finish here, with the reduction's arithmetic
         if (lane < nt && target_on(ia, ia.perm[t])) {
             const int64_t i = ia.perm[t];
             const double sc = X.scale * (double)mu;
-            ia.acc[i] = (float)(((double)ax - (double)cx) * sc);
-            ia.acc[N + i] = (float)(((double)ay - (double)cy) * sc);
-            ia.acc[2 * N + i] = (float)(((double)az - (double)cz) * sc);
+            ia.acc[i] = (float)(sx * sc);
+            ia.acc[N + i] = (float)(sy * sc);
+            ia.acc[2 * N + i] = (float)(sz * sc);
         }
         return;
     }
     // the compensated sum (times the equal mass, if any), rounded once
     float* o = partial + item * 3 * kBlock;
-    o[0 * kBlock + lane] = (float)(((double)ax - (double)cx) * (double)mu);
-    o[1 * kBlock + lane] = (float)(((double)ay - (double)cy) * (double)mu);
-    o[2 * kBlock + lane] = (float)(((double)az - (double)cz) * (double)mu);
+    o[0 * kBlock + lane] = (float)(sx * (double)mu);
+    o[1 * kBlock + lane] = (float)(sy * (double)mu);
+    o[2 * kBlock + lane] = (float)(sz * (double)mu);
 }
 
 // Monopoles (sec. 3.3, 1 to N): one wave per target block walks the block's
@@ -462,7 +492,8 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
                                                       unsigned long long* __restrict__ counter) {
     __shared__ float4 tile[2 * kBlock];
     const int64_t b = blockIdx.x;
-    if (b >= nblock) return;
+    if (ia.sizes[kSkip] || b >= ia.sizes[kNBlock]) return;
+    (void)nblock;
     if (ia.ioff[b + 1] == ia.ioff[b]) return;        // a block without active targets
     const int lane = threadIdx.x;
     const int xbox = ia.bboxid[b];
@@ -566,20 +597,24 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
 // Both forms are bounded to 80 VGPRs (6 waves per SIMD): two waves' VALU
 // instructions can issue in the same cycle, so more resident waves keep the
 // pair loop's issue slots fuller.
-template <int VAR>
-__global__ void __launch_bounds__(64, 6) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
-                                                    const float* __restrict__ mass_s, int64_t N,
-                                                    int64_t per_xcd, float* __restrict__ partial,
-                                                    unsigned long long* __restrict__ counters) {
-    __shared__ float4 tile[2 * kBlock];
+template <int VAR, int K>
+__global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
+                                                        const float* __restrict__ mass_s, int64_t N,
+                                                        float* __restrict__ partial,
+                                                        unsigned long long* __restrict__ counters) {
+    __shared__ float4 tile[K * 2 * kBlock];
+    __shared__ float4 qb[K * 8];
+    __shared__ double red[K > 1 ? K * 3 * kBlock : 1];
     __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
-    const int64_t item = xcd_item(blockIdx.x, per_xcd);
-    if (item >= ia.sizes[1]) return;
+    if (ia.sizes[kSkip]) return;
+    const int64_t nitem = ia.sizes[kNItem];
+    const int64_t item = xcd_item(blockIdx.x, (nitem + 7) / 8);
+    if (item >= nitem) return;
     if (VAR & 8) {
-        for (int k = threadIdx.x; k < kTabN; k += kBlock) tab[k] = ia.split_tab[k];
+        for (int k = threadIdx.x; k < kTabN; k += 64 * K) tab[k] = ia.split_tab[k];
         __syncthreads();
     }
-    pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab);
+    pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab, qb, red);
 }
 
 // Persistent form: a fixed grid of waves pulls items from 8 queues (one
@@ -587,20 +622,24 @@ __global__ void __launch_bounds__(64, 6) pp_f32_kernel(ItemArgs ia, const double
 // queue of its own XCD, then steals from the others.  Every wave leaves
 // once all queues are empty.  The item count is read from device memory,
 // so the launch can be replayed from a graph while the lists change.
-template <int VAR>
-__global__ void __launch_bounds__(64, 6) pp_f32_persistent(ItemArgs ia,
-                                                        const double* __restrict__ pos_s,
-                                                        const float* __restrict__ mass_s, int64_t N,
-                                                        float* __restrict__ partial,
-                                                        unsigned long long* __restrict__ counters,
-                                                        unsigned* __restrict__ queues) {
-    __shared__ float4 tile[2 * kBlock];
+template <int VAR, int K>
+__global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemArgs ia,
+                                                            const double* __restrict__ pos_s,
+                                                            const float* __restrict__ mass_s, int64_t N,
+                                                            float* __restrict__ partial,
+                                                            unsigned long long* __restrict__ counters,
+                                                            unsigned* __restrict__ queues) {
+    __shared__ float4 tile[K * 2 * kBlock];
+    __shared__ float4 qb[K * 8];
+    __shared__ double red[K > 1 ? K * 3 * kBlock : 1];
     __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
+    __shared__ unsigned next_item;
+    if (ia.sizes[kSkip]) return;
     if (VAR & 8) {
-        for (int k = threadIdx.x; k < kTabN; k += kBlock) tab[k] = ia.split_tab[k];
+        for (int k = threadIdx.x; k < kTabN; k += 64 * K) tab[k] = ia.split_tab[k];
         __syncthreads();
     }
-    const int64_t nitem = ia.sizes[1];
+    const int64_t nitem = ia.sizes[kNItem];
     const int64_t per = (nitem + 7) / 8;
     const int my = blockIdx.x & 7;
     for (int v = 0; v < 8; ++v) {
@@ -610,11 +649,19 @@ __global__ void __launch_bounds__(64, 6) pp_f32_persistent(ItemArgs ia,
         if (qbeg >= qend) continue;
         for (;;) {
             unsigned i = 0;
-            if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
-            i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
+            if (K == 1) {
+                if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
+                i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
+            } else {
+                // one pop per workgroup, shared through LDS
+                __syncthreads();
+                if (threadIdx.x == 0) next_item = atomicAdd(&queues[q], 1u);
+                __syncthreads();
+                i = next_item;
+            }
             const int64_t item = qbeg + (int64_t)i;
             if (item >= qend) break;
-            pp_item<VAR>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab);
+            pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab, qb, red);
         }
     }
 }
@@ -629,7 +676,8 @@ __global__ void __launch_bounds__(256) reduce_f32_kernel(ItemArgs ia,
                                                          const float* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
                                                          int64_t N, float* __restrict__ acc) {
-    const int64_t nblock = ia.sizes[0];
+    if (ia.sizes[kSkip]) return;
+    const int64_t nblock = ia.sizes[kNBlock];
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nblock * kBlock;
          g += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = g / kBlock;
@@ -681,15 +729,18 @@ __device__ __forceinline__ double split_factor_f64(double x) {
 template <bool COUNT>
 __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* __restrict__ pos_s,
                                                     const double* __restrict__ mass_s, int64_t N,
-                                                    int64_t per_xcd, double* __restrict__ partial,
+                                                    double* __restrict__ partial,
                                                     int32_t* __restrict__ pcount) {
-    const int64_t item = xcd_item(blockIdx.x, per_xcd);
-    if (item >= ia.sizes[1]) return;
+    if (ia.sizes[kSkip]) return;
+    const int64_t nitem = ia.sizes[kNItem];
+    const int64_t item = xcd_item(blockIdx.x, (nitem + 7) / 8);
+    if (item >= nitem) return;
     const int lane = threadIdx.x;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];
     const int32_t S = ia.slen[b];
-    const int32_t s1 = s0 + ia.chunk < S ? s0 + ia.chunk : S;
+    const int32_t chunk = (int32_t)ia.sizes[kChunk];
+    const int32_t s1 = s0 + chunk < S ? s0 + chunk : S;
     const BoxDev& X = ia.box[ia.bboxid[b]];
     const double L = X.L, rs = X.rs, rcut = X.rcut, eps = X.eps, G = X.G;
     const bool active = lane < ia.bcount[b];
@@ -765,7 +816,8 @@ __global__ void __launch_bounds__(256) reduce_f64_kernel(ItemArgs ia,
                                                          const double* __restrict__ partial,
                                                          const int32_t* __restrict__ perm,
                                                          int64_t N, double* __restrict__ acc) {
-    const int64_t nblock = ia.sizes[0];
+    if (ia.sizes[kSkip]) return;
+    const int64_t nblock = ia.sizes[kNBlock];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = g / kBlock;
     const int l = (int)(g % kBlock);
@@ -788,7 +840,8 @@ __global__ void __launch_bounds__(256) reduce_count_kernel(ItemArgs ia,
                                                            const int32_t* __restrict__ perm,
                                                            int64_t* __restrict__ counts,
                                                            unsigned long long* __restrict__ total) {
-    const int64_t nblock = ia.sizes[0];
+    if (ia.sizes[kSkip]) return;
+    const int64_t nblock = ia.sizes[kNBlock];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = g / kBlock;
     const int l = (int)(g % kBlock);
@@ -859,7 +912,7 @@ int launch_reset_queues(unsigned* queues, hipStream_t s) {
     return PP_OK;
 }
 
-template <int VAR>
+template <int VAR, int K>
 static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int waves_per_cu,
                              float* partial, unsigned long long* counters, unsigned* queues,
                              hipStream_t s) {
@@ -867,62 +920,79 @@ static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int w
         int dev = 0, cus = 256;
         PP_HIP(hipGetDevice(&dev));
         PP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const unsigned grid = (unsigned)(cus * (waves_per_cu > 0 ? waves_per_cu : 16));
-        hipLaunchKernelGGL(pp_f32_persistent<VAR>, dim3(grid), dim3(kBlock), 0, s, ia,
+        // waves_per_cu waves per CU in workgroups of K waves
+        const int wpc = waves_per_cu > 0 ? waves_per_cu : 16;
+        const unsigned grid = (unsigned)(cus * ((wpc + K - 1) / K));
+        hipLaunchKernelGGL((pp_f32_persistent<VAR, K>), dim3(grid), dim3(kBlock * K), 0, s, ia,
                            w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters,
                            queues);
     } else {
-        if (w.nitem == 0) return PP_OK;
-        const int64_t per = (w.nitem + 7) / 8;
-        hipLaunchKernelGGL(pp_f32_kernel<VAR>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
-                           w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, per, partial,
-                           counters);
+        // one workgroup per item, up to the item capacity (the count is on
+        // the device; the workgroups past it return at once)
+        const int64_t per = (w.cap_item + 7) / 8;
+        if (per == 0) return PP_OK;
+        hipLaunchKernelGGL((pp_f32_kernel<VAR, K>), dim3((unsigned)(per * 8)), dim3(kBlock * K), 0, s,
+                           ia, w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters);
     }
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_pp_f32(const BatchDev& bd, const Work& w, int groups, Mode mode, int waves_per_cu,
+template <int K>
+static int launch_pp_f32_k(const ItemArgs& ia, const Work& w, Mode mode, int waves_per_cu,
+                           int variant, float* partial, unsigned long long* counters,
+                           unsigned* queues, hipStream_t s) {
+    switch (variant) {
+        case 0: return launch_pp_f32_var<0, K>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 8: return launch_pp_f32_var<8, K>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        default: return fail(PP_EINVAL, "more than one wave per block needs variant 0 or 8");
+    }
+}
+
+int launch_pp_f32(const BatchDev& bd, const Work& w, int waves_per_block, Mode mode, int waves_per_cu,
                   int variant, float* partial, float* acc, unsigned long long* counters,
                   unsigned* queues, hipStream_t s) {
-    (void)groups;
-    ItemArgs ia = item_args(bd, w, 0);
+    ItemArgs ia = item_args(bd, w);
     ia.acc = acc;
+    if (waves_per_block == 2)
+        return launch_pp_f32_k<2>(ia, w, mode, waves_per_cu, variant & 15, partial, counters, queues, s);
+    if (waves_per_block == 4)
+        return launch_pp_f32_k<4>(ia, w, mode, waves_per_cu, variant & 15, partial, counters, queues, s);
     switch (variant & 15) {
-        case 0: return launch_pp_f32_var<0>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 1: return launch_pp_f32_var<1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 2: return launch_pp_f32_var<2>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 3: return launch_pp_f32_var<3>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 4: return launch_pp_f32_var<4>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 5: return launch_pp_f32_var<5>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 6: return launch_pp_f32_var<6>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 7: return launch_pp_f32_var<7>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 8: return launch_pp_f32_var<8>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 9: return launch_pp_f32_var<9>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 10: return launch_pp_f32_var<10>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 11: return launch_pp_f32_var<11>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 12: return launch_pp_f32_var<12>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 13: return launch_pp_f32_var<13>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        case 14: return launch_pp_f32_var<14>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
-        default: return launch_pp_f32_var<15>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 0: return launch_pp_f32_var<0, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 1: return launch_pp_f32_var<1, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 2: return launch_pp_f32_var<2, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 3: return launch_pp_f32_var<3, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 4: return launch_pp_f32_var<4, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 5: return launch_pp_f32_var<5, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 6: return launch_pp_f32_var<6, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 7: return launch_pp_f32_var<7, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 8: return launch_pp_f32_var<8, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 9: return launch_pp_f32_var<9, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 10: return launch_pp_f32_var<10, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 11: return launch_pp_f32_var<11, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 12: return launch_pp_f32_var<12, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 13: return launch_pp_f32_var<13, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        case 14: return launch_pp_f32_var<14, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
+        default: return launch_pp_f32_var<15, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
     }
 }
 
 int launch_monopole(const BatchDev& bd, const Work& w, float* acc, unsigned long long* counter,
                     hipStream_t s) {
-    if (w.nblock == 0 || !w.ent_final) return PP_OK;
-    ItemArgs ia = item_args(bd, w, 0);
+    if (w.cap_block == 0 || !w.ent_final) return PP_OK;
+    ItemArgs ia = item_args(bd, w);
     ia.acc = acc;
-    hipLaunchKernelGGL(monopole_kernel, dim3((unsigned)w.nblock), dim3(kBlock), 0, s, ia, w.ent_final,
+    hipLaunchKernelGGL(monopole_kernel, dim3((unsigned)w.cap_block), dim3(kBlock), 0, s, ia, w.ent_final,
                        w.eoff.as<int64_t>(), w.mono0, w.mono1, w.tviews.as<TreeView>(),
-                       w.tree_mc.as<double4>(), w.pos_s.as<double>(), w.pos_n, w.nblock, counter);
+                       w.tree_mc.as<double4>(), w.pos_s.as<double>(), w.pos_n, w.cap_block, counter);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
 int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, float* acc,
                       hipStream_t s) {
-    ItemArgs ia = item_args(bd, w, 0);
+    ItemArgs ia = item_args(bd, w);
     // a fixed grid (grid-stride) so a captured graph stays valid as nblock changes
     hipLaunchKernelGGL(reduce_f32_kernel, dim3(2048), dim3(256), 0, s, ia, partial,
                        w.perm.as<int32_t>(), w.pos_n, acc);
@@ -930,12 +1000,12 @@ int launch_reduce_f32(const BatchDev& bd, const Work& w, const float* partial, f
     return PP_OK;
 }
 
-int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial, hipStream_t s) {
-    if (w.nitem == 0) return PP_OK;
-    ItemArgs ia = item_args(bd, w, chunk);
-    const int64_t per = (w.nitem + 7) / 8;
+int launch_pp_f64(const BatchDev& bd, const Work& w, double* partial, hipStream_t s) {
+    const int64_t per = (w.cap_item + 7) / 8;
+    if (per == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w);
     hipLaunchKernelGGL(pp_f64_kernel<false>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
-                       w.pos_s.as<double>(), w.mass_sd.as<double>(), w.pos_n, per, partial,
+                       w.pos_s.as<double>(), w.mass_sd.as<double>(), w.pos_n, partial,
                        (int32_t*)nullptr);
     PP_HIP(hipGetLastError());
     return PP_OK;
@@ -943,20 +1013,20 @@ int launch_pp_f64(const BatchDev& bd, const Work& w, int chunk, double* partial,
 
 int launch_reduce_f64(const BatchDev& bd, const Work& w, const double* partial, double* acc,
                       hipStream_t s) {
-    if (w.nblock == 0) return PP_OK;
-    ItemArgs ia = item_args(bd, w, 0);
-    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(w.nblock * kBlock, 256)), dim3(256), 0, s,
+    if (w.cap_block == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w);
+    hipLaunchKernelGGL(reduce_f64_kernel, dim3(blocks_for(w.cap_block * kBlock, 256)), dim3(256), 0, s,
                        ia, partial, w.perm.as<int32_t>(), w.pos_n, acc);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
 
-int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial, hipStream_t s) {
-    if (w.nitem == 0) return PP_OK;
-    ItemArgs ia = item_args(bd, w, chunk);
-    const int64_t per = (w.nitem + 7) / 8;
+int launch_count(const BatchDev& bd, const Work& w, int32_t* partial, hipStream_t s) {
+    const int64_t per = (w.cap_item + 7) / 8;
+    if (per == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w);
     hipLaunchKernelGGL(pp_f64_kernel<true>, dim3((unsigned)(per * 8)), dim3(kBlock), 0, s, ia,
-                       w.pos_s.as<double>(), (const double*)nullptr, w.pos_n, per,
+                       w.pos_s.as<double>(), (const double*)nullptr, w.pos_n,
                        (double*)nullptr, partial);
     PP_HIP(hipGetLastError());
     return PP_OK;
@@ -964,9 +1034,9 @@ int launch_count(const BatchDev& bd, const Work& w, int chunk, int32_t* partial,
 
 int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partial, int64_t* counts,
                         unsigned long long* total, hipStream_t s) {
-    if (w.nblock == 0) return PP_OK;
-    ItemArgs ia = item_args(bd, w, 0);
-    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(w.nblock * kBlock, 256)), dim3(256), 0,
+    if (w.cap_block == 0) return PP_OK;
+    ItemArgs ia = item_args(bd, w);
+    hipLaunchKernelGGL(reduce_count_kernel, dim3(blocks_for(w.cap_block * kBlock, 256)), dim3(256), 0,
                        s, ia, partial, w.perm.as<int32_t>(), counts, total);
     PP_HIP(hipGetLastError());
     return PP_OK;

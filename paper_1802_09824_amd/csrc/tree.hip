@@ -116,10 +116,11 @@ __global__ void leaf_fill_kernel(const uint64_t* __restrict__ keys, const int8_t
 }
 
 __global__ void leaf_box_kernel(BatchDev bd, const double* __restrict__ pos_s, int64_t N,
-                                const int64_t* __restrict__ begin, int64_t m,
+                                const int64_t* __restrict__ begin, const int64_t* __restrict__ sizes,
                                 int32_t* __restrict__ count, IBox* __restrict__ box) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m) return;
+    const int64_t m = sizes[kNLeaf];
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m;
+         a += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b0 = begin[a], b1 = a + 1 < m ? begin[a + 1] : N;
     count[a] = (int32_t)(b1 - b0);
     const BoxDev& X = bd.box[box_of(bd.poff, bd.nbox, b0)];
@@ -136,6 +137,7 @@ __global__ void leaf_box_kernel(BatchDev bd, const double* __restrict__ pos_s, i
         B.hi[ax] = (int32_t)hi + 1;
     }
     box[a] = B;
+    }
 }
 
 // First leaf of every box: the first leaf starting at or after poff[x].
@@ -143,29 +145,80 @@ __global__ void leaf_box_kernel(BatchDev bd, const double* __restrict__ pos_s, i
 // starts a leaf, so the leaves before box x are the leaf starts before its
 // first particle, the exclusive flag scan at that index.
 __global__ void leaf_offsets_kernel(BatchDev bd, const int64_t* __restrict__ flag_off,
-                                    int64_t* __restrict__ loff) {
+                                    int64_t* __restrict__ loff, int64_t* __restrict__ sizes) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x > bd.nbox) return;
     loff[x] = flag_off[bd.poff[x]];
+    if (x == bd.nbox) sizes[kNLeaf] = loff[x];
 }
 
-// Sizes read from device memory by the graph-captured kernels.
-__global__ void set_sizes_kernel(int64_t* __restrict__ sizes, int64_t nblock, int64_t nitem,
-                                 int64_t nrange, int64_t nentry) {
-    if (threadIdx.x != 0) return;
-    sizes[0] = nblock;
-    sizes[1] = nitem;
-    sizes[2] = nrange;
-    sizes[3] = nentry;
-    for (int k = 4; k < 8; ++k) sizes[k] = 0;
+// Tree shape of every box from its leaf count (one workgroup): level h of
+// box x has cnt_h = ceil(cnt_{h-1} / 8) nodes while cnt_{h-1} > 1.  Level h
+// of all boxes is contiguous, boxes in order: lp[h (nbox + 1) + x] is the
+// number of level-h nodes of the boxes before x, and the levels follow one
+// another; total[0] receives the node count.
+__device__ __forceinline__ int64_t level_count(int64_t c0, int h) {
+    int64_t c = c0;
+    for (int k = 0; k < h; ++k) {
+        if (c <= 1) return 0;
+        c = (c + 7) / 8;
+    }
+    return c;
+}
+
+__global__ void __launch_bounds__(256) tree_views_kernel(const int64_t* __restrict__ loff, int nbox,
+                                                         TreeView* __restrict__ tv,
+                                                         int64_t* __restrict__ lp,
+                                                         int64_t* __restrict__ total) {
+    __shared__ int64_t part[256];
+    const int t = threadIdx.x;
+    const int per = (nbox + 255) / 256;
+    const int x0 = t * per < nbox ? t * per : nbox;
+    const int x1 = x0 + per < nbox ? x0 + per : nbox;
+    int64_t base = 0;                     // first node of level h (same in every thread)
+    for (int h = 0; h < kTreeMaxLevels; ++h) {
+        int64_t sum = 0;
+        for (int x = x0; x < x1; ++x) sum += level_count(loff[x + 1] - loff[x], h);
+        // inclusive scan of the 256 thread sums (Hillis-Steele in LDS)
+        part[t] = sum;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int64_t v = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        const int64_t level_total = part[255];
+        int64_t acc = part[t] - sum;      // nodes of this level before box x0
+        __syncthreads();
+        for (int x = x0; x < x1; ++x) {
+            const int64_t c0 = loff[x + 1] - loff[x];
+            const int64_t c = level_count(c0, h);
+            lp[(int64_t)h * (nbox + 1) + x] = acc;
+            TreeView& T = tv[x];
+            if (h == 0) {
+                int nl = 0;
+                while (nl < kTreeMaxLevels && level_count(c0, nl) > 0) ++nl;
+                T.nlev = c0 > 0 ? nl : 0;
+                T.loff = loff[x];
+                T.pad = 0;
+            }
+            T.cnt[h] = c;
+            T.off[h] = c > 0 ? base + acc : 0;
+            acc += c;
+        }
+        if (t == 0) lp[(int64_t)h * (nbox + 1) + nbox] = level_total;
+        base += level_total;
+    }
+    if (t == 0) total[0] = base;
 }
 
 // Level h >= 1 of every box's tree: node i of box x is the union of its
 // (up to 8) children.  lp = per-box prefix of the level's node counts.
 __global__ void tree_level_kernel(const TreeView* __restrict__ tv, const int64_t* __restrict__ lp,
                                   int nbox, int h, IBox* __restrict__ nodes) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= lp[nbox]) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < lp[nbox];
+         g += (int64_t)gridDim.x * blockDim.x) {
     const int x = box_of(lp, nbox, g);
     const TreeView& T = tv[x];
     const int64_t i = g - lp[x];
@@ -181,16 +234,18 @@ __global__ void tree_level_kernel(const TreeView* __restrict__ tv, const int64_t
         }
     }
     nodes[T.off[h] + i] = P;
+    }
 }
 
 // Mass and mass-weighted position sums of every tree node (x, y, z: sum of
 // m x; w: sum of m), FP64, for monopole acceptance.  Level 0 from the
 // particles of each leaf, in order; level h from its (up to 8) children.
 __global__ void leaf_moment_kernel(const double* __restrict__ pos_s, const float* __restrict__ mass_s,
-                                   int64_t N, const int64_t* __restrict__ begin, int64_t m,
-                                   double4* __restrict__ mc) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m) return;
+                                   int64_t N, const int64_t* __restrict__ begin,
+                                   const int64_t* __restrict__ sizes, double4* __restrict__ mc) {
+    const int64_t m = sizes[kNLeaf];
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m;
+         a += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b0 = begin[a], b1 = a + 1 < m ? begin[a + 1] : N;
     double sx = 0, sy = 0, sz = 0, sm = 0;
     for (int64_t k = b0; k < b1; ++k) {
@@ -201,12 +256,13 @@ __global__ void leaf_moment_kernel(const double* __restrict__ pos_s, const float
         sm += mk;
     }
     mc[a] = make_double4(sx, sy, sz, sm);
+    }
 }
 
 __global__ void tree_moment_kernel(const TreeView* __restrict__ tv, const int64_t* __restrict__ lp,
                                    int nbox, int h, double4* __restrict__ mc) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= lp[nbox]) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < lp[nbox];
+         g += (int64_t)gridDim.x * blockDim.x) {
     const int x = box_of(lp, nbox, g);
     const TreeView& T = tv[x];
     const int64_t i = g - lp[x];
@@ -222,6 +278,7 @@ __global__ void tree_moment_kernel(const TreeView* __restrict__ tv, const int64_
         P.w += C.w;
     }
     mc[T.off[h] + i] = P;
+    }
 }
 
 // ------------------------------------------------------------ box tests --
@@ -343,10 +400,10 @@ __device__ __forceinline__ bool accept_monopole(const IBox& A, const IBox& B, co
 // Smallest |a_ref|^2 over each block's targets (a_ref in input order).
 __global__ void block_amin_kernel(const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
                                   const int32_t* __restrict__ perm, const float* __restrict__ acc_ref,
-                                  int64_t N, int64_t nb, double* __restrict__ amin2) {
+                                  int64_t N, const int64_t* __restrict__ sizes, double* __restrict__ amin2) {
 #pragma clang fp contract(off)
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
+    if (b >= sizes[kNBlock]) return;
     double m = 0.0;
     for (int32_t k = 0; k < bcount[b]; ++k) {
         const int64_t i = perm[(int64_t)bstart[b] + k];
@@ -447,7 +504,7 @@ __global__ void __launch_bounds__(64) block_split_kernel(
     BatchDev bd, const double* __restrict__ pos_s, int64_t N, const int64_t* __restrict__ choff,
     int64_t nchunk, int32_t* __restrict__ ccount, const int64_t* __restrict__ coff,
     int32_t* __restrict__ bstart, int32_t* __restrict__ bcount, IBox* __restrict__ box,
-    int32_t* __restrict__ bboxid) {
+    int32_t* __restrict__ bboxid, int64_t cap) {
     const int64_t c = blockIdx.x;
     if (c >= nchunk) return;
     const int lane = threadIdx.x;
@@ -473,6 +530,7 @@ __global__ void __launch_bounds__(64) block_split_kernel(
         if (lane == 0) {
             if (FILL) {
                 const int64_t o = coff[c];
+                if (o >= cap) return;          // too many blocks: reported by the count
                 bstart[o] = (int32_t)k0;
                 bcount[o] = (int32_t)(k1 - k0);
                 IBox B;
@@ -495,7 +553,7 @@ __global__ void __launch_bounds__(64) block_split_kernel(
     int64_t start = k0;
     IBox B;
     auto emit = [&](int64_t e) {
-        if (FILL) {
+        if (FILL && o + nb < cap) {
             bstart[o + nb] = (int32_t)start;
             bcount[o + nb] = (int32_t)(e - start);
             box[o + nb] = B;
@@ -578,11 +636,16 @@ __device__ __forceinline__ void expand2(const TreeView& tv, const IBox* nodes, i
 template <bool FILL>
 __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                 const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
-                                const int32_t* __restrict__ bboxid, int64_t nb,
-                                int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                FEntry* __restrict__ out, MonoDev mono) {
+                                const int32_t* __restrict__ bboxid, const int64_t* __restrict__ sizes,
+                                int64_t cap_in, int32_t* __restrict__ cnt,
+                                const int64_t* __restrict__ off, FEntry* __restrict__ out,
+                                int64_t cap_out, MonoDev mono) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
+    if (b >= cap_in) return;
+    if (b >= sizes[kNBlock]) {
+        if (!FILL) cnt[b] = 0;
+        return;
+    }
     const int x = bboxid[b];
     const TreeView& tv = tvs[x];
     const int64_t W = bd.box[x].W, T = bd.box[x].T;
@@ -607,7 +670,8 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
             e.inside = maxd2_shift(A, R, s, W) < T;
             e.mono = (mono.theta2 > 0.0 || mono.alpha > 0.0) && top >= kMonoMinLevel &&
                      accept_monopole(A, R, s, W, mono, tv.off[top], b, bd.box[x].G, bd.box[x].cell);
-            out[o++] = e;
+            if (o < cap_out) out[o] = e;
+            ++o;
         } else {
             ++c;
         }
@@ -621,18 +685,25 @@ template <bool FILL>
 __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                  const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                  const int32_t* __restrict__ bboxid, const FEntry* __restrict__ in,
-                                 int64_t F, int stop, int32_t* __restrict__ cnt,
-                                 const int64_t* __restrict__ off, FEntry* __restrict__ out,
-                                 MonoDev mono) {
+                                 const int64_t* __restrict__ F_in, int64_t cap_in, int stop,
+                                 int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
+                                 FEntry* __restrict__ out, int64_t cap_out, MonoDev mono) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= F) return;
+    if (e >= cap_in) return;
+    if (e >= *F_in) {
+        if (!FILL) cnt[e] = 0;
+        return;
+    }
     const FEntry E = in[e];
     // with monopole acceptance, inside entries are opened too (a child may
     // be accepted); accepted entries are final
     const bool mono_on = mono.theta2 > 0.0 || mono.alpha > 0.0;
     if (E.mono || E.lev <= stop || (E.inside && !mono_on)) {
-        if (FILL) out[off[e]] = E;
-        else cnt[e] = 1;
+        if (FILL) {
+            if (off[e] < cap_out) out[off[e]] = E;
+        } else {
+            cnt[e] = 1;
+        }
         return;
     }
     const int x = bboxid[E.blk];
@@ -657,7 +728,8 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
         C.mono = mono_on && C.lev >= kMonoMinLevel &&
                  accept_monopole(bbox[E.blk], nodes[tvs[x].off[C.lev] + C.node], s, bd.box[x].W, mono,
                                  tvs[x].off[C.lev] + C.node, E.blk, bd.box[x].G, bd.box[x].cell);
-        out[o++] = C;
+        if (o < cap_out) out[o] = C;
+        ++o;
     }
 }
 
@@ -678,9 +750,21 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                               const int64_t* __restrict__ eoff, int32_t* __restrict__ rbeg,
                               int32_t* __restrict__ rpre, uint8_t* __restrict__ rcode,
                               MonoDev mono, uint64_t* __restrict__ mono0,
-                              uint8_t* __restrict__ mono1) {
+                              uint8_t* __restrict__ mono1, const int64_t* __restrict__ sizes,
+                              int64_t cap_range) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= F) return;
+    if (e >= F) return;                       // F: the capacity of the entry buffer
+    if (e >= sizes[kNEntry]) {
+        if (!FILL) {
+            rcnt[e] = 0;
+            scnt[e] = 0;
+            if (mono0) {
+                mono0[e] = 0;
+                mono1[e] = 0;
+            }
+        }
+        return;
+    }
     const FEntry E = ent[e];
     const int x = bboxid[E.blk];
     const TreeView& tv = tvs[x];
@@ -701,9 +785,11 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
         const int64_t p0 = leaf_begin[tv.loff + l0];
         const int64_t p1 = leaf_begin[tv.loff + l1] + leaf_count[tv.loff + l1];
         if (FILL) {
-            rbeg[o] = (int32_t)p0;
-            rpre[o] = (int32_t)pos;
-            rcode[o] = E.sc;
+            if (o < cap_range) {
+                rbeg[o] = (int32_t)p0;
+                rpre[o] = (int32_t)pos;
+                rcode[o] = E.sc;
+            }
             ++o;
         }
         ++nr;
@@ -790,10 +876,11 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
 }
 
 // First entry of every block (entries are sorted by block).
-__global__ void block_entry_kernel(const FEntry* __restrict__ ent, int64_t F, int64_t nblock,
-                                   int64_t* __restrict__ eoff) {
+__global__ void block_entry_kernel(const FEntry* __restrict__ ent, const int64_t* __restrict__ sizes,
+                                   int64_t cap_block, int64_t* __restrict__ eoff) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > nblock) return;
+    const int64_t nblock = sizes[kNBlock], F = sizes[kNEntry];
+    if (b > nblock || b > cap_block) return;
     int64_t lo = 0, hi = F;             // first e with ent[e].blk >= b
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -805,36 +892,49 @@ __global__ void block_entry_kernel(const FEntry* __restrict__ ent, int64_t F, in
 
 // Per-block range offsets and list lengths; flags a list longer than int32.
 __global__ void block_sum_kernel(const int64_t* __restrict__ eoff, const int64_t* __restrict__ roff_e,
-                                 const int64_t* __restrict__ soff_e, int64_t nblock,
-                                 int64_t* __restrict__ roff, int32_t* __restrict__ slen,
-                                 int* __restrict__ overflow) {
+                                 const int64_t* __restrict__ soff_e, int64_t* __restrict__ sizes,
+                                 int64_t cap_block, int64_t* __restrict__ roff,
+                                 int32_t* __restrict__ slen) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > nblock) return;
+    const int64_t nblock = sizes[kNBlock];
+    if (b > nblock || b > cap_block) return;
     roff[b] = roff_e[eoff[b]];
     if (b == nblock) return;
     const int64_t len = soff_e[eoff[b + 1]] - soff_e[eoff[b]];
-    if (len > INT32_MAX) atomicOr(overflow, 1);
+    if (len > INT32_MAX) atomicOr(reinterpret_cast<unsigned long long*>(sizes + kOverflow), 16ull);
     slen[b] = (int32_t)(len < INT32_MAX ? len : INT32_MAX);
 }
 
-// Total listed sources (sum of the block list lengths).
-__global__ void total_sources_kernel(const int64_t* __restrict__ soff_e, int64_t F,
-                                     int64_t* __restrict__ out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *out = soff_e[F];
+// Listed sources in all (sum of the block list lengths) and the effective
+// chunk: the requested one, or larger when the item partial sums (3 x 64
+// floats per item) would pass max_items items.
+__global__ void chunk_kernel(const int64_t* __restrict__ soff_e, int64_t* __restrict__ sizes,
+                             int64_t chunk_req, int64_t max_items) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t total = soff_e[sizes[kNEntry]];
+    sizes[kTotalSrc] = total;
+    int64_t chunk = chunk_req;
+    const int64_t need = (total + max_items - 1) / max_items;
+    if (need > chunk) chunk = ((need + kBlock - 1) / kBlock) * kBlock;
+    if (chunk > INT32_MAX / 2) chunk = INT32_MAX / 2;
+    sizes[kChunk] = chunk;
 }
 
 // Work items per block: its list in chunks (at least one item, so that every
 // target is written); none for a block without an active target when flags
 // are given.
 __global__ void item_count_kernel(const int32_t* __restrict__ slen,
-                                  const int32_t* __restrict__ bcount, int64_t nblock, int chunk,
-                                  const uint8_t* __restrict__ active,
+                                  const int32_t* __restrict__ bcount, int64_t* __restrict__ sizes,
+                                  int64_t cap_block, const uint8_t* __restrict__ active,
                                   const int32_t* __restrict__ perm,
                                   const int32_t* __restrict__ bstart,
-                                  int32_t* __restrict__ icount,
-                                  unsigned long long* __restrict__ cand) {
+                                  int32_t* __restrict__ icount) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblock) return;
+    if (b >= cap_block) return;
+    if (b >= sizes[kNBlock]) {
+        icount[b] = 0;
+        return;
+    }
     if (active) {
         bool on = false;
         for (int32_t k = 0; k < bcount[b] && !on; ++k) on = active[perm[(int64_t)bstart[b] + k]] != 0;
@@ -844,152 +944,192 @@ __global__ void item_count_kernel(const int32_t* __restrict__ slen,
         }
     }
     const int32_t s = slen[b];
-    icount[b] = s <= 0 ? 1 : (s + chunk - 1) / chunk;
+    const int64_t chunk = sizes[kChunk];
+    icount[b] = s <= 0 ? 1 : (int32_t)((s + chunk - 1) / chunk);
     // (target, listed source) pairs; the kernel prunes some sources further
-    atomicAdd(cand, (unsigned long long)s * (unsigned long long)bcount[b]);
+    atomicAdd(reinterpret_cast<unsigned long long*>(sizes + kCand),
+              (unsigned long long)s * (unsigned long long)bcount[b]);
 }
 
 __global__ void item_fill_kernel(const int32_t* __restrict__ icount,
-                                 const int64_t* __restrict__ ioff, int64_t nblock, int chunk,
-                                 int32_t* __restrict__ iblock, int32_t* __restrict__ is0) {
+                                 const int64_t* __restrict__ ioff, const int64_t* __restrict__ sizes,
+                                 int64_t cap_item, int32_t* __restrict__ iblock,
+                                 int32_t* __restrict__ is0) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblock) return;
+    if (b >= sizes[kNBlock]) return;
     const int64_t o = ioff[b];
+    const int64_t chunk = sizes[kChunk];
     for (int32_t c = 0; c < icount[b]; ++c) {
+        if (o + c >= cap_item) return;
         iblock[o + c] = (int32_t)b;
-        is0[o + c] = c * chunk;
+        is0[o + c] = (int32_t)(c * chunk);
     }
+}
+
+// count slot <- min(total, cap); need slot <- total; overflow bit when over
+__global__ void note_count_kernel(int64_t* __restrict__ sizes, const int64_t* __restrict__ total,
+                                  int slot, int need_slot, int64_t cap, unsigned long long bit) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t t = *total;
+    sizes[need_slot] = t;
+    sizes[slot] = t < cap ? t : cap;
+    if (t > cap) sizes[kOverflow] |= (int64_t)bit;
+}
+
+// Item and range totals, and the flag that makes the PP kernels return.
+__global__ void finish_sizes_kernel(int64_t* __restrict__ sizes, const int64_t* __restrict__ ioff,
+                                    const int64_t* __restrict__ roff, int64_t cap_item,
+                                    int64_t cap_range, const int* __restrict__ bad) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t nb = sizes[kNBlock];
+    const int64_t ni = ioff[nb], nr = roff[nb];
+    sizes[kNeedItem] = ni;
+    sizes[kNeedRange] = nr;
+    sizes[kNItem] = ni < cap_item ? ni : cap_item;
+    sizes[kNRange] = nr < cap_range ? nr : cap_range;
+    if (ni > cap_item) sizes[kOverflow] |= 8;
+    if (nr > cap_range) sizes[kOverflow] |= 4;
+    sizes[kBad] = bad ? *bad : 0;
+    sizes[kSkip] = (sizes[kOverflow] != 0 || sizes[kBad] != 0) ? 1 : 0;
+}
+
+__global__ void zero_sizes_kernel(int64_t* __restrict__ sizes) {
+    if (threadIdx.x < kSizeSlots) sizes[threadIdx.x] = 0;
 }
 
 }  // namespace
 
+// A grid for a grid-stride loop over at most n items.
+static unsigned stride_grid(int64_t n, int t) {
+    const int64_t b = (n + t - 1) / t;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+// Nodes of the implicit trees over at most n leaves in nbox boxes: the
+// leaves plus at most n / 7 + 1 nodes per level above them in every box.
+static int64_t tree_node_bound(int64_t n, int nbox) {
+    const int64_t m = n > 0 ? n : 1;
+    return m + m / 7 + (int64_t)nbox * kTreeMaxLevels + 8;
+}
+
+// Levels of the implicit tree over at most n leaves.
+static int levels_for(int64_t n) {
+    int h = 1;
+    int64_t c = n > 0 ? n : 1;
+    while (c > 1 && h < kTreeMaxLevels) {
+        c = (c + 7) / 8;
+        ++h;
+    }
+    return h;
+}
+
+int reset_sizes(Work& w, hipStream_t s) {
+    PP_TRY(w.sizes.reserve(sizeof(int64_t) * kSizeSlots));
+    hipLaunchKernelGGL(zero_sizes_kernel, dim3(1), dim3(kSizeSlots), 0, s, w.sizes.as<int64_t>());
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
 int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, const double* pos_s,
-                 Work& w, hipStream_t s, const int* bad_dev, int* bad_host) {
-    w.nleaf = 0;
-    w.loff.assign(bd.nbox + 1, 0);
-    if (N == 0) return PP_OK;
+                 Work& w, hipStream_t s) {
+    PP_TRY(w.sizes.reserve(sizeof(int64_t) * kSizeSlots));
+    PP_TRY(w.loff_dev.reserve(sizeof(int64_t) * (bd.nbox + 1)));
     const int M = bd.leaf_max;
     const int64_t len = N + M;
+    const int64_t m = N > 0 ? N : 1;        // leaves: at most one per particle
     PP_TRY(w.lam.reserve(len + 1));
     PP_TRY(w.pmax.reserve(len + 1));
     PP_TRY(w.smax.reserve(len + 1));
     PP_TRY(w.level_p.reserve(N + 1));
     PP_TRY(w.flag.reserve(sizeof(int32_t) * (N + 1)));
     PP_TRY(w.flag_off.reserve(sizeof(int64_t) * (N + 2)));
-    hipLaunchKernelGGL(lam_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, bd, sorted_keys, N,
-                       w.lam.as<int8_t>());
-    const int64_t nblk = (len + M) / (M + 1);
-    hipLaunchKernelGGL(vhgw_kernel, dim3(blocks_for(nblk, 256)), dim3(256), 0, s,
-                       w.lam.as<int8_t>(), len, M + 1, w.pmax.as<int8_t>(), w.smax.as<int8_t>());
-    hipLaunchKernelGGL(level_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, w.pmax.as<int8_t>(),
-                       w.smax.as<int8_t>(), N, M, bd.bits, w.level_p.as<int8_t>());
-    hipLaunchKernelGGL(flag_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, sorted_keys,
-                       w.level_p.as<int8_t>(), N, w.flag.as<int32_t>());
-    PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N, w.scan_ws, s));
-    PP_TRY(w.loff_dev.reserve(sizeof(int64_t) * (bd.nbox + 1)));
-    hipLaunchKernelGGL(leaf_offsets_kernel, dim3(blocks_for(bd.nbox + 1, 64)), dim3(64), 0, s, bd,
-                       w.flag_off.as<int64_t>(), w.loff_dev.as<int64_t>());
-    PP_HIP(hipGetLastError());
-    // one read-back: the per-box leaf offsets (total at the end) and, when
-    // asked, the input-check flag
-    PP_HIP(hipMemcpyAsync(w.loff.data(), w.loff_dev.p, sizeof(int64_t) * (bd.nbox + 1),
-                          hipMemcpyDeviceToHost, s));
-    if (bad_dev) PP_HIP(hipMemcpyAsync(bad_host, bad_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    PP_HIP(hipStreamSynchronize(s));
-    const int64_t m = w.loff[bd.nbox];
     PP_TRY(w.lbegin.reserve(sizeof(int64_t) * (m + 1)));
     PP_TRY(w.lcount.reserve(sizeof(int32_t) * (m + 1)));
     PP_TRY(w.llevel.reserve(sizeof(int32_t) * (m + 1)));
     PP_TRY(w.lprefix.reserve(sizeof(uint64_t) * (m + 1)));
-    PP_TRY(w.lboxes.reserve(sizeof(IBox) * (m + 1)));
-    hipLaunchKernelGGL(leaf_fill_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, sorted_keys,
-                       w.level_p.as<int8_t>(), w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N,
-                       bd.bits, w.lbegin.as<int64_t>(), w.llevel.as<int32_t>(),
-                       w.lprefix.as<uint64_t>());
-    hipLaunchKernelGGL(leaf_box_kernel, dim3(blocks_for(m, 128)), dim3(128), 0, s, bd, pos_s, N,
-                       w.lbegin.as<int64_t>(), m, w.lcount.as<int32_t>(), w.lboxes.as<IBox>());
+    // the leaf boxes are level 0 of the trees' node array (leaf a of the
+    // batch is node a): the tree levels go after them
+    PP_TRY(w.tree_boxes.reserve(sizeof(IBox) * tree_node_bound(N, bd.nbox)));
+    if (N > 0) {
+        hipLaunchKernelGGL(lam_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, bd, sorted_keys, N,
+                           w.lam.as<int8_t>());
+        const int64_t nblk = (len + M) / (M + 1);
+        hipLaunchKernelGGL(vhgw_kernel, dim3(blocks_for(nblk, 256)), dim3(256), 0, s,
+                           w.lam.as<int8_t>(), len, M + 1, w.pmax.as<int8_t>(), w.smax.as<int8_t>());
+        hipLaunchKernelGGL(level_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, w.pmax.as<int8_t>(),
+                           w.smax.as<int8_t>(), N, M, bd.bits, w.level_p.as<int8_t>());
+        hipLaunchKernelGGL(flag_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, sorted_keys,
+                           w.level_p.as<int8_t>(), N, w.flag.as<int32_t>());
+        PP_HIP(hipGetLastError());
+    }
+    PP_TRY(launch_scan_i32_to_i64(w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N, w.scan_ws, s));
+    hipLaunchKernelGGL(leaf_offsets_kernel, dim3(blocks_for(bd.nbox + 1, 64)), dim3(64), 0, s, bd,
+                       w.flag_off.as<int64_t>(), w.loff_dev.as<int64_t>(), w.sizes.as<int64_t>());
     PP_HIP(hipGetLastError());
-    w.nleaf = m;
+    if (N > 0) {
+        hipLaunchKernelGGL(leaf_fill_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, sorted_keys,
+                           w.level_p.as<int8_t>(), w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N,
+                           bd.bits, w.lbegin.as<int64_t>(), w.llevel.as<int32_t>(),
+                           w.lprefix.as<uint64_t>());
+        hipLaunchKernelGGL(leaf_box_kernel, dim3(stride_grid(N, 128)), dim3(128), 0, s, bd, pos_s, N,
+                           w.lbegin.as<int64_t>(), w.sizes.as<int64_t>(), w.lcount.as<int32_t>(),
+                           w.tree_boxes.as<IBox>());
+        PP_HIP(hipGetLastError());
+    }
     return PP_OK;
 }
 
-int stage_trees(const BatchDev& bd, Work& w, hipStream_t s) {
+int leaves_to_host(const BatchDev& bd, Work& w, hipStream_t s) {
+    w.loff.assign(bd.nbox + 1, 0);
+    PP_HIP(hipMemcpyAsync(w.loff.data(), w.loff_dev.p, sizeof(int64_t) * (bd.nbox + 1),
+                          hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    w.nleaf = w.loff[bd.nbox];
+    return PP_OK;
+}
+
+int stage_trees(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
     const int nbox = bd.nbox;
-    w.tv.assign(nbox, TreeView{});
-    // level sizes per box
-    std::vector<std::vector<int64_t>> cnt(nbox);
-    int maxlev = 0;
-    for (int x = 0; x < nbox; ++x) {
-        int64_t c = w.loff[x + 1] - w.loff[x];
-        if (c == 0) continue;
-        for (;;) {
-            cnt[x].push_back(c);
-            if (c <= 1) break;
-            c = (c + 7) / 8;
-        }
-        if ((int)cnt[x].size() > kTreeMaxLevels) return fail(PP_ERANGE, "tree too deep");
-        maxlev = (int)cnt[x].size() > maxlev ? (int)cnt[x].size() : maxlev;
-    }
-    w.max_levels = maxlev;
-    // layout: level h of all boxes contiguous, boxes in order
-    std::vector<int64_t> lp((size_t)kTreeMaxLevels * (nbox + 1), 0);
-    std::vector<int64_t> base(kTreeMaxLevels + 1, 0);
-    for (int h = 0; h < maxlev; ++h) {
-        int64_t acc = 0;
-        for (int x = 0; x < nbox; ++x) {
-            lp[(size_t)h * (nbox + 1) + x] = acc;
-            if ((int)cnt[x].size() > h) acc += cnt[x][h];
-        }
-        lp[(size_t)h * (nbox + 1) + nbox] = acc;
-        base[h + 1] = base[h] + acc;
-    }
-    for (int x = 0; x < nbox; ++x) {
-        TreeView& T = w.tv[x];
-        T.nlev = (int32_t)cnt[x].size();
-        T.loff = w.loff[x];
-        for (int h = 0; h < kTreeMaxLevels; ++h) {
-            T.cnt[h] = h < T.nlev ? cnt[x][h] : 0;
-            T.off[h] = h < T.nlev ? base[h] + lp[(size_t)h * (nbox + 1) + x] : 0;
-        }
-    }
-    const int64_t total = base[maxlev];
-    PP_TRY(w.tree_boxes.reserve(sizeof(IBox) * (total > 0 ? total : 1)));
+    const int H = levels_for(N);
+    w.max_levels = H;
+    PP_TRY(w.tree_boxes.reserve(sizeof(IBox) * tree_node_bound(N, nbox)));
     PP_TRY(w.tviews.reserve(sizeof(TreeView) * nbox));
-    PP_TRY(w.lvl_prefix.reserve(sizeof(int64_t) * lp.size()));
-    PP_HIP(hipMemcpyAsync(w.tviews.p, w.tv.data(), sizeof(TreeView) * nbox, hipMemcpyHostToDevice, s));
-    PP_HIP(hipMemcpyAsync(w.lvl_prefix.p, lp.data(), sizeof(int64_t) * lp.size(),
-                          hipMemcpyHostToDevice, s));
-    w.lvl_prefix_host = lp;
-    IBox* nodes = w.tree_boxes.as<IBox>();
-    if (w.nleaf > 0)
-        PP_HIP(hipMemcpyAsync(nodes, w.lboxes.p, sizeof(IBox) * w.nleaf, hipMemcpyDeviceToDevice, s));
-    for (int h = 1; h < maxlev; ++h) {
-        const int64_t nh = lp[(size_t)h * (nbox + 1) + nbox];
-        hipLaunchKernelGGL(tree_level_kernel, dim3(blocks_for(nh, 256)), dim3(256), 0, s,
+    PP_TRY(w.lvl_prefix.reserve(sizeof(int64_t) * (size_t)kTreeMaxLevels * (nbox + 1)));
+    PP_TRY(w.tree_total.reserve(sizeof(int64_t) * 2));
+    hipLaunchKernelGGL(tree_views_kernel, dim3(1), dim3(256), 0, s, w.loff_dev.as<int64_t>(), nbox,
+                       w.tviews.as<TreeView>(), w.lvl_prefix.as<int64_t>(), w.tree_total.as<int64_t>());
+    PP_HIP(hipGetLastError());
+    IBox* nodes = w.tree_boxes.as<IBox>();       // level 0: the leaf boxes (stage_leaves)
+    int64_t bound = N;
+    for (int h = 1; h < H; ++h) {
+        bound = (bound + 7) / 8 + nbox;
+        hipLaunchKernelGGL(tree_level_kernel, dim3(stride_grid(bound, 256)), dim3(256), 0, s,
                            w.tviews.as<TreeView>(), w.lvl_prefix.as<int64_t>() + (size_t)h * (nbox + 1),
                            nbox, h, nodes);
     }
     PP_HIP(hipGetLastError());
-    // the host vectors above must outlive the asynchronous copies
+    return PP_OK;
+}
+
+int trees_to_host(const BatchDev& bd, Work& w, hipStream_t s) {
+    w.tv.assign(bd.nbox, TreeView{});
+    PP_HIP(hipMemcpyAsync(w.tv.data(), w.tviews.p, sizeof(TreeView) * bd.nbox, hipMemcpyDeviceToHost, s));
     PP_HIP(hipStreamSynchronize(s));
     return PP_OK;
 }
 
-int stage_node_moments(const BatchDev& bd, Work& w, hipStream_t s) {
+int stage_node_moments(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
     const int nbox = bd.nbox;
-    int64_t total = 0;
-    for (int x = 0; x < nbox; ++x)
-        for (int h = 0; h < w.tv[x].nlev; ++h) total += w.tv[x].cnt[h];
-    PP_TRY(w.tree_mc.reserve(sizeof(double4) * (total > 0 ? total : 1)));
-    if (w.nleaf == 0) return PP_OK;
-    const int64_t N = w.pos_n;
+    PP_TRY(w.tree_mc.reserve(sizeof(double4) * tree_node_bound(N, nbox)));
+    if (N == 0) return PP_OK;
     double4* mc = w.tree_mc.as<double4>();
-    hipLaunchKernelGGL(leaf_moment_kernel, dim3(blocks_for(w.nleaf, 128)), dim3(128), 0, s,
-                       w.pos_s.as<double>(), w.mass_s.as<float>(), N, w.lbegin.as<int64_t>(), w.nleaf, mc);
+    hipLaunchKernelGGL(leaf_moment_kernel, dim3(stride_grid(N, 128)), dim3(128), 0, s,
+                       w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, w.lbegin.as<int64_t>(),
+                       w.sizes.as<int64_t>(), mc);
+    int64_t bound = N;
     for (int h = 1; h < w.max_levels; ++h) {
-        const int64_t nh = w.lvl_prefix_host[(size_t)h * (nbox + 1) + nbox];
-        hipLaunchKernelGGL(tree_moment_kernel, dim3(blocks_for(nh, 256)), dim3(256), 0, s,
+        bound = (bound + 7) / 8 + nbox;
+        hipLaunchKernelGGL(tree_moment_kernel, dim3(stride_grid(bound, 256)), dim3(256), 0, s,
                            w.tviews.as<TreeView>(), w.lvl_prefix.as<int64_t>() + (size_t)h * (nbox + 1),
                            nbox, h, mc);
     }
@@ -1001,7 +1141,7 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
                           DevBuf& row_ptr, DevBuf& src, DevBuf& code, DevBuf& scan_ws,
                           int64_t* nentries, hipStream_t s) {
     (void)bd;
-    const int64_t nleaf = w.nleaf;
+    const int64_t nleaf = w.nleaf;     // host copies: leaves_to_host, trees_to_host
     PP_TRY(row_cnt.reserve(sizeof(int32_t) * (nleaf + 1)));
     PP_TRY(row_ptr.reserve(sizeof(int64_t) * (nleaf + 1)));
     *nentries = 0;
@@ -1029,45 +1169,84 @@ int build_canonical_pairs(const BatchDev& bd, const Work& w, int64_t W, int64_t 
     return PP_OK;
 }
 
+// Capacities start from estimates and grow to 5/4 of what a pass needed
+// whenever a buffer was too small (lists_to_host); the pass then runs again.
+static int64_t grow_cap(int64_t cap, int64_t need) {
+    if (need <= cap) return cap;
+    return need + need / 4 + 1024;
+}
+
+// After a pass that fitted: a capacity far above the need comes down to it
+// (plus the margin).
+static int64_t settle_cap(int64_t cap, int64_t need) {
+    const int64_t want = need + need / 4 + 1024;
+    return cap > 2 * want ? want : cap;
+}
+
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
                 hipStream_t s, const MonoCfg& mcfg, const uint8_t* active) {
     const int nbox = bd.nbox;
     const int64_t N = poff[nbox];
-    w.nblock = w.nentry = w.nrange = w.nitem = w.candidates = 0;
-    // chunks of kBlock particles inside each box
+    int64_t* sizes = w.sizes.as<int64_t>();
+    // chunks of kBlock particles inside each box (offsets change only with
+    // the box sizes; uploaded synchronously then)
     std::vector<int64_t> choff(nbox + 1, 0);
     for (int x = 0; x < nbox; ++x)
         choff[x + 1] = choff[x] + (poff[x + 1] - poff[x] + kBlock - 1) / kBlock;
     const int64_t nc = choff[nbox];
     w.nchunk = nc;
-    if (nc == 0) return PP_OK;
     PP_TRY(w.choff.reserve(sizeof(int64_t) * (nbox + 1)));
-    PP_HIP(hipMemcpyAsync(w.choff.p, choff.data(), sizeof(int64_t) * (nbox + 1), hipMemcpyHostToDevice, s));
-    PP_TRY(w.ccount.reserve(sizeof(int32_t) * nc));
-    PP_TRY(w.coff.reserve(sizeof(int64_t) * (nc + 1)));
+    if (choff != w.choff_h) {
+        PP_HIP(hipMemcpy(w.choff.p, choff.data(), sizeof(int64_t) * (nbox + 1), hipMemcpyHostToDevice));
+        w.choff_h = choff;
+    }
+    // capacities: blocks from the chunks, the rest from the last need
+    if (w.cap_block < nc + nc / 8 + 64) w.cap_block = nc + nc / 8 + 64;
+    const int64_t cb = w.cap_block;
+    if (w.cap_ent[0] < 4 * cb) w.cap_ent[0] = 4 * cb;
+    PP_TRY(w.ccount.reserve(sizeof(int32_t) * (nc + 1)));
+    PP_TRY(w.coff.reserve(sizeof(int64_t) * (nc + 2)));
+    PP_TRY(w.bstart.reserve(sizeof(int32_t) * cb));
+    PP_TRY(w.bcount.reserve(sizeof(int32_t) * cb));
+    PP_TRY(w.bbox.reserve(sizeof(IBox) * cb));
+    PP_TRY(w.bboxid.reserve(sizeof(int32_t) * cb));
+    PP_TRY(w.slen.reserve(sizeof(int32_t) * cb));
+    PP_TRY(w.roff.reserve(sizeof(int64_t) * (cb + 2)));
+    PP_TRY(w.icount.reserve(sizeof(int32_t) * (cb + 1)));
+    PP_TRY(w.ioff.reserve(sizeof(int64_t) * (cb + 2)));
+    PP_TRY(w.eoff.reserve(sizeof(int64_t) * (cb + 2)));
+    // expansion passes (see below) and their entry capacities: the root pass
+    // and H - 2 lowering passes, the last of which (level 2 to 1) is left
+    // out when it would need too many entries
+    const int H = w.max_levels;
+    int nlower = H > 2 ? H - 2 : 0;
+    const bool to_level1 = !w.stop_at_level2 || nlower == 0;
+    if (!to_level1) nlower -= 1;
+    const int npass = 1 + nlower;
+    w.npass = npass;
+    for (int p = 0; p < npass; ++p)
+        if (w.cap_ent[p] < 1024) w.cap_ent[p] = p == 0 ? 4 * cb : w.cap_ent[p - 1] * 2;
+    int64_t capcnt = cb;
+    for (int p = 0; p < npass; ++p) capcnt = w.cap_ent[p] > capcnt ? w.cap_ent[p] : capcnt;
+    // the scans' workspace for the largest scan of the pass, reserved before
+    // the first one is enqueued
+    PP_TRY(grow_scan(w.scan_ws, capcnt > nc ? capcnt : nc));
     const double* pos_s = w.pos_s.as<double>();
-    hipLaunchKernelGGL(block_split_kernel<false>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
-                       pos_s, N, w.choff.as<int64_t>(), nc, w.ccount.as<int32_t>(),
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-                       (IBox*)nullptr, (int32_t*)nullptr);
-    PP_HIP(hipGetLastError());
+    if (nc > 0) {
+        hipLaunchKernelGGL(block_split_kernel<false>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
+                           pos_s, N, w.choff.as<int64_t>(), nc, w.ccount.as<int32_t>(),
+                           (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                           (IBox*)nullptr, (int32_t*)nullptr, cb);
+        PP_HIP(hipGetLastError());
+    }
     PP_TRY(launch_scan_i32_to_i64(w.ccount.as<int32_t>(), w.coff.as<int64_t>(), nc, w.scan_ws, s));
-    int64_t nb = 0;
-    PP_TRY(read_back(w.coff.as<int64_t>() + nc, &nb, s));   // also orders the choff upload
-    w.nblock = nb;
-    PP_TRY(w.bstart.reserve(sizeof(int32_t) * nb));
-    PP_TRY(w.bcount.reserve(sizeof(int32_t) * nb));
-    PP_TRY(w.bbox.reserve(sizeof(IBox) * nb));
-    PP_TRY(w.bboxid.reserve(sizeof(int32_t) * nb));
-    PP_TRY(w.slen.reserve(sizeof(int32_t) * nb));
-    PP_TRY(w.roff.reserve(sizeof(int64_t) * (nb + 1)));
-    PP_TRY(w.icount.reserve(sizeof(int32_t) * nb));
-    PP_TRY(w.ioff.reserve(sizeof(int64_t) * (nb + 1)));
-    PP_TRY(w.misc.reserve(64));
-    hipLaunchKernelGGL(block_split_kernel<true>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
-                       pos_s, N, w.choff.as<int64_t>(), nc, (int32_t*)nullptr,
-                       w.coff.as<int64_t>(), w.bstart.as<int32_t>(), w.bcount.as<int32_t>(),
-                       w.bbox.as<IBox>(), w.bboxid.as<int32_t>());
+    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.coff.as<int64_t>() + nc,
+                       (int)kNBlock, (int)kNeedBlock, cb, 1ull);
+    if (nc > 0)
+        hipLaunchKernelGGL(block_split_kernel<true>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
+                           pos_s, N, w.choff.as<int64_t>(), nc, (int32_t*)nullptr,
+                           w.coff.as<int64_t>(), w.bstart.as<int32_t>(), w.bcount.as<int32_t>(),
+                           w.bbox.as<IBox>(), w.bboxid.as<int32_t>(), cb);
     PP_HIP(hipGetLastError());
     const TreeView* tvs = w.tviews.as<TreeView>();
     const IBox* nodes = w.tree_boxes.as<IBox>();
@@ -1075,56 +1254,65 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     const int32_t* bboxid = w.bboxid.as<int32_t>();
     MonoDev mono{mcfg.theta2, mcfg.alpha, mcfg.mc, nullptr};
     if (mcfg.alpha > 0.0) {
-        PP_TRY(w.blk_amin2.reserve(sizeof(double) * (nb + 1)));
-        hipLaunchKernelGGL(block_amin_kernel, dim3(blocks_for(nb, 128)), dim3(128), 0, s,
+        PP_TRY(w.blk_amin2.reserve(sizeof(double) * (cb + 1)));
+        hipLaunchKernelGGL(block_amin_kernel, dim3(blocks_for(cb, 128)), dim3(128), 0, s,
                            w.bstart.as<int32_t>(), w.bcount.as<int32_t>(), w.perm.as<int32_t>(),
-                           mcfg.acc_ref, w.pos_n, nb, w.blk_amin2.as<double>());
+                           mcfg.acc_ref, w.pos_n, sizes, w.blk_amin2.as<double>());
         PP_HIP(hipGetLastError());
         mono.amin2 = w.blk_amin2.as<double>();
     }
-    // breadth-first from every box's root down to the DFS level
+    // Breadth-first expansion from every box's root: pass 0 takes the roots,
+    // every later pass lowers the entries above level 2 by one level and the
+    // last pass lowers level 2 to level 1 (when it does not exceed the entry
+    // budget), so that the depth-first walks cover at most 8 (else 64)
+    // leaves each; passes beyond a box's depth carry its entries unchanged.
+    // Entry buffers alternate between two arrays.
+    int64_t cap_a = 0, cap_b = 0;
+    for (int p = 0; p < npass; ++p) {
+        int64_t& c = p % 2 == 0 ? cap_a : cap_b;
+        c = w.cap_ent[p] > c ? w.cap_ent[p] : c;
+    }
+    PP_TRY(w.fent_a.reserve(sizeof(FEntry) * (cap_a + 1)));
+    PP_TRY(w.fent_b.reserve(sizeof(FEntry) * (cap_b + 1)));
+    PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (capcnt + 1)));
+    PP_TRY(w.foff.reserve(sizeof(int64_t) * (capcnt + 2)));
+    hipLaunchKernelGGL(bfs_root_kernel<false>, dim3(blocks_for(cb, 128)), dim3(128), 0, s, bd, tvs,
+                       nodes, bbox, bboxid, (const int64_t*)sizes, cb, w.fcnt.as<int32_t>(),
+                       (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
+    PP_HIP(hipGetLastError());
+    PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cb, w.scan_ws, s));
+    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cb,
+                       (int)kEntry0, (int)kNeedEntry0, w.cap_ent[0], 2ull);
+    hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(cb, 128)), dim3(128), 0, s, bd, tvs,
+                       nodes, bbox, bboxid, (const int64_t*)sizes, cb, (int32_t*)nullptr,
+                       w.foff.as<int64_t>(), w.fent_a.as<FEntry>(), w.cap_ent[0], mono);
+    PP_HIP(hipGetLastError());
     DevBuf* cur = &w.fent_a;
     DevBuf* nxt = &w.fent_b;
-    int64_t F = 0;
-    PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (nb + 1)));
-    PP_TRY(w.foff.reserve(sizeof(int64_t) * (nb + 2)));
-    hipLaunchKernelGGL(bfs_root_kernel<false>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
-                       nodes, bbox, bboxid, nb, w.fcnt.as<int32_t>(), (const int64_t*)nullptr,
-                       (FEntry*)nullptr, mono);
-    PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), nb, w.scan_ws, s));
-    PP_TRY(read_back(w.foff.as<int64_t>() + nb, &F, s));
-    PP_TRY(cur->reserve(sizeof(FEntry) * (F + 1)));
-    hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(nb, 128)), dim3(128), 0, s, bd, tvs,
-                       nodes, bbox, bboxid, nb, (int32_t*)nullptr, w.foff.as<int64_t>(),
-                       cur->as<FEntry>(), mono);
-    PP_HIP(hipGetLastError());
-    // Levels above kDfsLevel must be expanded (the masks cover 64 leaves);
-    // level 2 -> 1 is taken too when the expanded entries fit the budget.
-    constexpr int64_t kEntryBudget = (int64_t)1 << 27;
-    for (int it = w.max_levels - 1; it >= kDfsLevel; --it) {
-        const int stop = it == kDfsLevel ? kDfsLevel - 1 : kDfsLevel;
-        PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (F + 1)));
-        PP_TRY(w.foff.reserve(sizeof(int64_t) * (F + 2)));
-        hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd,
-                           tvs, nodes, bbox, bboxid, cur->as<FEntry>(), F, stop,
-                           w.fcnt.as<int32_t>(), (const int64_t*)nullptr, (FEntry*)nullptr, mono);
+    for (int p = 1; p < npass; ++p) {
+        const int stop = (p == npass - 1 && to_level1) ? kDfsLevel - 1 : kDfsLevel;
+        const int64_t cin = w.cap_ent[p - 1], cout = w.cap_ent[p];
+        hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd,
+                           tvs, nodes, bbox, bboxid, cur->as<FEntry>(),
+                           (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, w.fcnt.as<int32_t>(),
+                           (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
         PP_HIP(hipGetLastError());
-        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), F, w.scan_ws, s));
-        int64_t F2 = 0;
-        PP_TRY(read_back(w.foff.as<int64_t>() + F, &F2, s));
-        if (it == kDfsLevel && F2 > kEntryBudget) break;      // stay at level 2
-        PP_TRY(nxt->reserve(sizeof(FEntry) * (F2 + 1)));
-        hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
-                           nodes, bbox, bboxid, cur->as<FEntry>(), F, stop, (int32_t*)nullptr,
-                           w.foff.as<int64_t>(), nxt->as<FEntry>(), mono);
+        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cin, w.scan_ws, s));
+        hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cin,
+                           (int)(kEntry0 + p), (int)(kNeedEntry0 + p), cout, 2ull);
+        hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd, tvs,
+                           nodes, bbox, bboxid, cur->as<FEntry>(),
+                           (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, (int32_t*)nullptr,
+                           w.foff.as<int64_t>(), nxt->as<FEntry>(), cout, mono);
         PP_HIP(hipGetLastError());
         DevBuf* t = cur;
         cur = nxt;
         nxt = t;
-        F = F2;
     }
-    w.nentry = F;
+    const int64_t F = w.cap_ent[npass - 1];    // the final entry buffer's capacity
+    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes,
+                       (const int64_t*)(sizes + kEntry0 + npass - 1), (int)kNEntry,
+                       (int)(kNeedEntry0 + kMaxPasses - 1), F, 0ull);
     const FEntry* ent = cur->as<FEntry>();
     w.ent_final = ent;
     PP_TRY(w.lmask_e.reserve(sizeof(uint64_t) * (F + 1)));
@@ -1132,7 +1320,6 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.scnt_e.reserve(sizeof(int32_t) * (F + 1)));
     PP_TRY(w.roff_e.reserve(sizeof(int64_t) * (F + 2)));
     PP_TRY(w.soff_e.reserve(sizeof(int64_t) * (F + 2)));
-    PP_TRY(w.eoff.reserve(sizeof(int64_t) * (nb + 2)));
     const int64_t* lbegin = w.lbegin.as<int64_t>();
     const int32_t* lcount = w.lcount.as<int32_t>();
     uint64_t* mono0 = nullptr;
@@ -1145,74 +1332,86 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     }
     w.mono0 = mono0;
     w.mono1 = mono1;
+    if (w.cap_range < 1024) w.cap_range = 16 * cb;
+    if (w.cap_item < 1024) w.cap_item = 2 * cb;
     hipLaunchKernelGGL(ranges_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
                        w.rcnt_e.as<int32_t>(), w.scnt_e.as<int32_t>(), (const int64_t*)nullptr,
                        (const int64_t*)nullptr, (const int64_t*)nullptr, (int32_t*)nullptr,
-                       (int32_t*)nullptr, (uint8_t*)nullptr, mono, mono0, mono1);
-    hipLaunchKernelGGL(block_entry_kernel, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, ent, F,
-                       nb, w.eoff.as<int64_t>());
+                       (int32_t*)nullptr, (uint8_t*)nullptr, mono, mono0, mono1,
+                       (const int64_t*)sizes, w.cap_range);
+    hipLaunchKernelGGL(block_entry_kernel, dim3(blocks_for(cb + 1, 256)), dim3(256), 0, s, ent,
+                       (const int64_t*)sizes, cb, w.eoff.as<int64_t>());
     PP_HIP(hipGetLastError());
     PP_TRY(launch_scan_i32_to_i64(w.rcnt_e.as<int32_t>(), w.roff_e.as<int64_t>(), F, w.scan_ws, s));
     PP_TRY(launch_scan_i32_to_i64(w.scnt_e.as<int32_t>(), w.soff_e.as<int64_t>(), F, w.scan_ws, s));
-    unsigned long long* cand = w.misc.as<unsigned long long>();
-    int* ovf = reinterpret_cast<int*>(cand + 1);
-    PP_HIP(hipMemsetAsync(cand, 0, 2 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(block_sum_kernel, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s,
-                       w.eoff.as<int64_t>(), w.roff_e.as<int64_t>(), w.soff_e.as<int64_t>(), nb,
-                       w.roff.as<int64_t>(), w.slen.as<int32_t>(), ovf);
-    // The chunk grows when the lists are so long that the item partial sums
-    // (6 x 64 floats per item) would pass kMaxItems items.
-    int64_t total_src = 0;
-    hipLaunchKernelGGL(total_sources_kernel, dim3(1), dim3(64), 0, s, w.soff_e.as<int64_t>(), F,
-                       reinterpret_cast<int64_t*>(cand + 2));
-    PP_HIP(hipGetLastError());
-    PP_TRY(read_back(reinterpret_cast<int64_t*>(cand + 2), &total_src, s));
+    hipLaunchKernelGGL(block_sum_kernel, dim3(blocks_for(cb + 1, 256)), dim3(256), 0, s,
+                       w.eoff.as<int64_t>(), w.roff_e.as<int64_t>(), w.soff_e.as<int64_t>(), sizes, cb,
+                       w.roff.as<int64_t>(), w.slen.as<int32_t>());
     constexpr int64_t kMaxItems = 1 << 21;
-    int64_t chunk64 = chunk_req;
-    const int64_t need = (total_src + kMaxItems - 1) / kMaxItems;
-    if (need > chunk64) chunk64 = ((need + kBlock - 1) / kBlock) * kBlock;
-    if (chunk64 > INT32_MAX / 2) chunk64 = INT32_MAX / 2;
-    const int chunk = (int)chunk64;
-    w.chunk = chunk;
+    hipLaunchKernelGGL(chunk_kernel, dim3(1), dim3(1), 0, s, w.soff_e.as<int64_t>(), sizes,
+                       (int64_t)chunk_req, kMaxItems);
     w.active = active;
-    hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(nb, 256)), dim3(256), 0, s,
-                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), nb, chunk, active,
-                       w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>(), cand);
+    hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
+                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), sizes, cb, active,
+                       w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>());
     PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), nb, w.scan_ws, s));
-    int64_t hostv[2];
-    unsigned long long hc[2] = {0, 0};
-    PP_HIP(hipMemcpyAsync(&hostv[0], w.roff.as<int64_t>() + nb, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, s));
-    PP_HIP(hipMemcpyAsync(&hostv[1], w.ioff.as<int64_t>() + nb, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, s));
-    PP_HIP(hipMemcpyAsync(hc, cand, sizeof(hc), hipMemcpyDeviceToHost, s));
-    PP_HIP(hipStreamSynchronize(s));
-    if (hc[1] & 0xffffffffull) return fail(PP_ERANGE, "a target block lists more than 2^31 sources");
-    w.nrange = hostv[0];
-    w.nitem = hostv[1];
-    w.candidates = (int64_t)hc[0];
-    PP_TRY(w.rbeg.reserve(sizeof(int32_t) * (w.nrange + 1)));
-    PP_TRY(w.rpre.reserve(sizeof(int32_t) * (w.nrange + 1)));
-    PP_TRY(w.rcode.reserve(sizeof(uint8_t) * (w.nrange + 1)));
-    PP_TRY(w.iblock.reserve(sizeof(int32_t) * (w.nitem + 1)));
-    PP_TRY(w.is0.reserve(sizeof(int32_t) * (w.nitem + 1)));
+    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), cb, w.scan_ws, s));
+    PP_TRY(w.rbeg.reserve(sizeof(int32_t) * (w.cap_range + 1)));
+    PP_TRY(w.rpre.reserve(sizeof(int32_t) * (w.cap_range + 1)));
+    PP_TRY(w.rcode.reserve(sizeof(uint8_t) * (w.cap_range + 1)));
+    PP_TRY(w.iblock.reserve(sizeof(int32_t) * (w.cap_item + 1)));
+    PP_TRY(w.is0.reserve(sizeof(int32_t) * (w.cap_item + 1)));
     hipLaunchKernelGGL(ranges_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
                        (int32_t*)nullptr, (int32_t*)nullptr, w.roff_e.as<int64_t>(),
                        w.soff_e.as<int64_t>(), w.eoff.as<int64_t>(), w.rbeg.as<int32_t>(),
                        w.rpre.as<int32_t>(), w.rcode.as<uint8_t>(), mono, (uint64_t*)nullptr,
-                       (uint8_t*)nullptr);
-    hipLaunchKernelGGL(item_fill_kernel, dim3(blocks_for(nb, 256)), dim3(256), 0, s,
-                       w.icount.as<int32_t>(), w.ioff.as<int64_t>(), nb, chunk,
+                       (uint8_t*)nullptr, (const int64_t*)sizes, w.cap_range);
+    hipLaunchKernelGGL(item_fill_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
+                       w.icount.as<int32_t>(), w.ioff.as<int64_t>(), (const int64_t*)sizes, w.cap_item,
                        w.iblock.as<int32_t>(), w.is0.as<int32_t>());
+    hipLaunchKernelGGL(finish_sizes_kernel, dim3(1), dim3(1), 0, s, sizes, w.ioff.as<int64_t>(),
+                       w.roff.as<int64_t>(), w.cap_item, w.cap_range, w.bad.as<int>());
     PP_HIP(hipGetLastError());
-    // sizes read by graph-captured kernels
-    PP_TRY(w.sizes.reserve(sizeof(int64_t) * 8));
-    hipLaunchKernelGGL(set_sizes_kernel, dim3(1), dim3(64), 0, s, w.sizes.as<int64_t>(), w.nblock,
-                       w.nitem, w.nrange, w.nentry);
-    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
+int lists_to_host(Work& w, hipStream_t s, bool* regrow) {
+    *regrow = false;
+    PP_TRY(w.sizes_h.reserve(sizeof(int64_t) * kSizeSlots));
+    int64_t* h = w.sizes_h.as<int64_t>();
+    PP_HIP(hipMemcpyAsync(h, w.sizes.p, sizeof(int64_t) * kSizeSlots, hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    if (h[kBad]) return fail(PP_EINVAL, "non-finite position or mass");
+    if (h[kOverflow] & 16) return fail(PP_ERANGE, "a target block lists more than 2^31 sources");
+    if (h[kOverflow]) {
+        w.cap_block = grow_cap(w.cap_block, h[kNeedBlock]);
+        int np = w.npass;
+        if (!w.stop_at_level2 && np >= 2 && h[kNeedEntry0 + np - 1] > kEntryBudget) {
+            // the level-1 pass would be too large: stop at level 2 from now on
+            w.stop_at_level2 = true;
+            np -= 1;
+        }
+        for (int p = 0; p < np; ++p) w.cap_ent[p] = grow_cap(w.cap_ent[p], h[kNeedEntry0 + p]);
+        w.cap_range = grow_cap(w.cap_range, h[kNeedRange]);
+        w.cap_item = grow_cap(w.cap_item, h[kNeedItem]);
+        *regrow = true;
+        return PP_OK;
+    }
+    // capacities follow the needs (the buffers keep their size): scans and
+    // grids then span little more than the data
+    w.cap_block = settle_cap(w.cap_block, h[kNeedBlock]);
+    for (int p = 0; p < w.npass; ++p) w.cap_ent[p] = settle_cap(w.cap_ent[p], h[kNeedEntry0 + p]);
+    w.cap_range = settle_cap(w.cap_range, h[kNeedRange]);
+    w.cap_item = settle_cap(w.cap_item, h[kNeedItem]);
+    w.nleaf = h[kNLeaf];
+    w.nblock = h[kNBlock];
+    w.nentry = h[kNEntry];
+    w.nrange = h[kNRange];
+    w.nitem = h[kNItem];
+    w.candidates = h[kCand];
+    w.chunk = (int)h[kChunk];
     return PP_OK;
 }
 

@@ -144,7 +144,11 @@ def test_graph_recaptured_after_smaller_n(pp):
 
 @pytest.mark.parametrize("tuning", [dict(persistent=1, waves_per_cu=4), dict(chunk=256),
                                     dict(chunk=64, persistent=1, waves_per_cu=1),
-                                    dict(persistent=1, use_graph=1, waves_per_cu=32)])
+                                    dict(persistent=1, use_graph=1, waves_per_cu=32),
+                                    dict(waves_per_block=2), dict(waves_per_block=4, chunk=8192),
+                                    dict(waves_per_block=4, chunk=256, persistent=0),
+                                    dict(waves_per_block=2, persistent=1, use_graph=1, waves_per_cu=7),
+                                    dict(waves_per_block=4, variant=8)])
 def test_launch_shapes_agree(pp, tuning):
     b = W.make_config(1)
     plan = pp.Plan(b.params, b.n)
@@ -152,17 +156,53 @@ def test_launch_shapes_agree(pp, tuning):
     base = plan.accel(p, m).cpu().numpy()
     plan.set_tuning(**tuning)
     got = plan.accel(p, m).cpu().numpy()
-    if "chunk" in tuning:
-        # a different chunk changes the work items and so the summation order
+    again = plan.accel(p, m).cpu().numpy()
+    assert np.array_equal(got, again)                # reproducible for a given tuning
+    if "chunk" in tuning or "waves_per_block" in tuning or "variant" in tuning:
+        # a different chunk or split among waves changes the summation order
         assert np.allclose(got, base, rtol=1e-5, atol=1e-6 * np.abs(base).max())
     else:
         assert np.array_equal(got, base)
 
 
+@pytest.mark.parametrize("k,persistent", [(2, 1), (4, 1), (4, 0)])
+def test_waves_per_block_vs_oracle(pp, oracle_mod, k, persistent):
+    """K waves sharing a target block: the oracle's tolerances on the 32k
+    box and on a ragged clustered box with lists spanning several items."""
+    for b in (W.make_config(1),
+              W.Box(pos=W.mixture(np.random.default_rng(41), 9001, 40.0, 0.8, 6),
+                    mass=np.random.default_rng(42).uniform(0.5, 1.5, 9001).astype(np.float32),
+                    params=BoxParams.from_mesh(40.0, 20), name="ragged")):
+        plan = pp.Plan(b.params, b.n)
+        plan.set_tuning(waves_per_block=k, persistent=persistent, chunk=256 * k)
+        acc = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()
+        assert plan.stats()["nitem"] > plan.stats()["nblock"]
+        ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, pair_abs=True)
+        s = parity.summary(acc, ref)
+        assert s["zero_ok"] and s["median"] <= 1e-6 and s["p999"] <= 1e-4, (b.name, s)
+        assert s["robust_max"] <= parity.ROBUST_MAX, (b.name, s)
+
+
+def test_batch_bit_identical_with_waves_per_block(pp):
+    boxes = small_batch(5, seed=17)
+    pos, mass = concat(boxes)
+    bp = pp.BatchPlan([b.params for b in boxes], [b.n for b in boxes])
+    bp.set_tuning(waves_per_block=4, chunk=1024)
+    acc = bp.accel(dev(pos, torch.float64), dev(mass, torch.float32)).cpu().numpy()
+    off = 0
+    for b in boxes:
+        plan = pp.Plan(b.params, b.n)
+        plan.set_tuning(waves_per_block=4, chunk=1024)
+        a1 = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()
+        assert np.array_equal(acc[:, off:off + b.n], a1), b.name
+        off += b.n
+
+
 def test_tuning_validation(pp):
     b = W.make_config(1)
     plan = pp.Plan(b.params, b.n)
-    for bad in [dict(chunk=100), dict(chunk=0), dict(waves_per_cu=0), dict(use_graph=1, persistent=0)]:
+    for bad in [dict(chunk=100), dict(chunk=0), dict(waves_per_cu=0), dict(use_graph=1, persistent=0),
+                dict(waves_per_block=3), dict(waves_per_block=0), dict(waves_per_block=2, variant=1)]:
         with pytest.raises(pp.PPError):
             plan.set_tuning(**{**dict(chunk=4096, persistent=0, waves_per_cu=16, use_graph=0), **bad})
 
