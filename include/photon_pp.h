@@ -164,6 +164,22 @@ int pp_accel(pp_plan* plan, const double* pos, const float* mass, int64_t n, flo
  * with n > 0. */
 int pp_accel_active(pp_plan* plan, const double* pos, const float* mass, int64_t n,
                     const uint8_t* active, float* acc, void* stream);
+/* pp_accel without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  No plan: one box of p with at most 65536 particles,
+ * the default tuning of a plan, every device buffer carved from one static
+ * device array of 64 MiB that each device holds until the process ends (no
+ * hipMalloc, hipFree or allocating library call; host bookkeeping only).
+ * The results are those of pp_accel on a plan with the default tuning.
+ * The array is shared by all calls on a device and keeps the last call's
+ * contents (every buffer is written before it is read); calls on one device
+ * from several host threads are serialised by a lock (unsynchronised they
+ * would race on the array).  Synchronises the stream.
+ * Errors: as pp_accel; PP_EINVAL for n > 65536; PP_ENOMEM when the input's
+ * lists need more than the 64 MiB (possible for very clustered inputs near
+ * the particle limit). */
+int pp_accel_scratch(const pp_box_params* p, const double* pos, const float* mass, int64_t n,
+                     float* acc, void* stream);
 /* The same sum entirely in FP64 (accuracy yardstick).                     */
 int pp_accel_f64(pp_plan* plan, const double* pos, const double* mass, int64_t n, double* acc,
                  void* stream);

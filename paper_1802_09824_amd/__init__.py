@@ -71,6 +71,7 @@ _SIGS = {
     "pp_plan_destroy": (None, [_P]),
     "pp_accel": (_i32, [_P, _P, _P, _i64, _P, _P]),
     "pp_accel_f64": (_i32, [_P, _P, _P, _i64, _P, _P]),
+    "pp_accel_scratch": (_i32, [C.POINTER(pp_box_params), _P, _P, _i64, _P, _P]),
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
     "pp_plan_set_monopole": (_i32, [_P, C.c_double]),
     "pp_accel_active": (_i32, [_P, _P, _P, _i64, _P, _P, _P]),
@@ -350,6 +351,21 @@ class Plan:
         _check(_lib.pp_count_interactions(self._h, ptr, C.byref(tot), _stream(stream)),
                "pp_count_interactions")
         return (int(tot.value), counts) if per_target else int(tot.value)
+
+
+def pp_accel_scratch(params, pos: torch.Tensor, mass: torch.Tensor, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """pp_accel without allocation: one box of at most 65536 particles, every
+    buffer in the library's static device scratch."""
+    n = pos.shape[1]
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+    prm = make_params(params)
+    _check(_lib.pp_accel_scratch(C.byref(prm), _dev(pos, torch.float64, (3, n), "pos"),
+                                 _dev(mass, torch.float32, (n,), "mass"), n,
+                                 _dev(out, torch.float32, (3, n), "acc"), _stream(stream)),
+           "pp_accel_scratch")
+    return out
 
 
 def pp_plan_create(params, n_max: int) -> Plan:

@@ -6,8 +6,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -36,9 +38,26 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
 
 uint64_t alloc_generation() { return g_alloc_generation; }
 
+static thread_local Arena* t_arena = nullptr;
+
+ScratchScope::ScratchScope(Arena* a) : prev(t_arena) { t_arena = a; }
+ScratchScope::~ScratchScope() { t_arena = prev; }
+
 int DevBuf::reserve(size_t need) {
     if (need <= bytes) return PP_OK;
     release();
+    if (t_arena) {
+        const size_t want = (need + 255) & ~(size_t)255;
+        if (t_arena->used + want > t_arena->cap)
+            return fail(PP_ENOMEM, "the input needs more than the static device scratch of the "
+                                   "allocation-free entry point holds");
+        p = t_arena->base + t_arena->used;
+        t_arena->used += want;
+        bytes = want;
+        carved = true;
+        ++g_alloc_generation;
+        return PP_OK;
+    }
     const size_t want = need + need / 4 + 256;
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
@@ -55,16 +74,32 @@ int DevBuf::reserve(size_t need) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && !carved) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    carved = false;
+}
+
+static void host_free(HostBuf& h) {
+    if (h.p) {
+        if (h.pinned) (void)hipHostFree(h.p);
+        else std::free(h.p);
+    }
+    h.p = nullptr;
+    h.bytes = 0;
 }
 
 int HostBuf::reserve(size_t need) {
     if (need <= bytes) return PP_OK;
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    bytes = 0;
+    host_free(*this);
+    if (t_arena) {                      // no HIP allocation at all: plain host memory
+        p = std::malloc(need);
+        if (!p) return fail(PP_ENOMEM, "host allocation failed");
+        pinned = false;
+        bytes = need;
+        return PP_OK;
+    }
+    pinned = true;
     hipError_t e = hipHostMalloc(&p, need, hipHostMallocDefault);
     if (e != hipSuccess) {
         p = nullptr;
@@ -75,9 +110,7 @@ int HostBuf::reserve(size_t need) {
     return PP_OK;
 }
 
-HostBuf::~HostBuf() {
-    if (p) (void)hipHostFree(p);
-}
+HostBuf::~HostBuf() { host_free(*this); }
 
 BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
     BoxDev b{};
@@ -810,6 +843,32 @@ int pp_accel(pp_plan* pl, const double* pos, const float* mass, int64_t n, float
     return pl->b.accel_f32(pos, mass, acc, S(stream));
 }
 
+// ------------------------------------------------- allocation-free path --
+// Every buffer of pp_accel_scratch comes from one static device array of
+// kScratchBytes (each device holds its own copy until the process ends).  In
+// host code `scratch` is only a host-side stand-in: the device address is
+// taken once per device with hipGetSymbolAddress, with that device current,
+// and only that address reaches kernels and copies.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int64_t kScratchMaxN = 65536;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu[kScratchDevices];
+static char* g_scratch_ptr[kScratchDevices];
+
+// The device address of this device's scratch (g_scratch_mu[dev] held, dev current).
+static int scratch_address(int dev, char** out) {
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        if (!ptr) return fail(PP_EDEVICE, "hipGetSymbolAddress(scratch) gave no address");
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return PP_OK;
+}
+
 int pp_accel_active(pp_plan* pl, const double* pos, const float* mass, int64_t n,
                     const uint8_t* active, float* acc, void* stream) {
     PP_TRY(check_accel_args(pl, pos, mass, n, acc));
@@ -817,6 +876,52 @@ int pp_accel_active(pp_plan* pl, const double* pos, const float* mass, int64_t n
     if (n == 0) return PP_OK;
     PP_TRY(plan_resize(pl, n));
     return pl->b.accel_f32(pos, mass, acc, S(stream), active);
+}
+
+int pp_accel_scratch(const pp_box_params* p, const double* pos, const float* mass, int64_t n,
+                     float* acc, void* stream) {
+    PP_TRY(validate_params(p, true));
+    if (n < 0 || n > kScratchMaxN)
+        return fail(PP_EINVAL, "pp_accel_scratch takes at most 65536 particles (the static scratch)");
+    PP_TRY(check_ptr(pos, n, "pos"));
+    PP_TRY(check_ptr(mass, n, "mass"));
+    PP_TRY(check_ptr(acc, n, "acc"));
+    if (n == 0) return PP_OK;
+    int dev = 0;
+    PP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return fail(PP_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    char* base = nullptr;
+    PP_TRY(scratch_address(dev, &base));
+    Arena arena{base, kScratchBytes, 0};
+    ScratchScope scope(&arena);
+    hipStream_t s = S(stream);
+    // the list capacities of the last attempt (a pass that overflowed runs
+    // again, every buffer carved afresh from the start of the array)
+    int64_t cap_block = 0, cap_range = 0, cap_item = 0;
+    int64_t cap_ent[kMaxPasses] = {};
+    bool stop2 = false;
+    for (int attempt = 0; attempt < 32; ++attempt) {
+        arena.used = 0;
+        Batch b;
+        PP_TRY(b.init(1, p, &n));
+        b.w.cap_block = cap_block;
+        b.w.cap_range = cap_range;
+        b.w.cap_item = cap_item;
+        for (int k = 0; k < kMaxPasses; ++k) b.w.cap_ent[k] = cap_ent[k];
+        b.w.stop_at_level2 = stop2;
+        PP_TRY(b.prepare(pos, mass, nullptr, s));
+        PP_TRY(b.run_f32(acc, s));
+        bool again = false;
+        PP_TRY(b.finish(s, &again));
+        if (!again) return PP_OK;
+        cap_block = b.w.cap_block;
+        cap_range = b.w.cap_range;
+        cap_item = b.w.cap_item;
+        for (int k = 0; k < kMaxPasses; ++k) cap_ent[k] = b.w.cap_ent[k];
+        stop2 = b.w.stop_at_level2;
+    }
+    return fail(PP_ENOMEM, "the list buffers kept growing");
 }
 
 int pp_accel_f64(pp_plan* pl, const double* pos, const double* mass, int64_t n, double* acc,

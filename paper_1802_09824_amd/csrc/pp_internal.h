@@ -37,9 +37,23 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line);
 // --------------------------------------------------------- device memory --
 // Grow-only device buffer.  Contents are not preserved across growth; every
 // growth bumps a global generation so cached graphs can notice.
+// Bump region of device memory that DevBuf::reserve carves buffers from
+// instead of calling hipMalloc while a ScratchScope is active on the thread
+// (the allocation-free entry point); such buffers are never freed.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+};
+struct ScratchScope {
+    explicit ScratchScope(Arena* a);
+    ~ScratchScope();
+    Arena* prev;
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool carved = false;     // carved from an Arena (not hipMalloc'ed)
     int reserve(size_t need);
     void release();
     template <class T> T* as() const { return static_cast<T*>(p); }
@@ -175,6 +189,7 @@ constexpr int64_t kEntryBudget = (int64_t)1 << 28;
 struct HostBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool pinned = false;     // hipHostMalloc'ed (else plain host memory, under a ScratchScope)
     int reserve(size_t need);
     template <class T> T* as() const { return static_cast<T*>(p); }
     ~HostBuf();
