@@ -93,6 +93,9 @@ def parse():
                     help="skip the 16.8M precision and 134M large-box legs")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tiles instead of running the autotuner first")
+    ap.add_argument("--tuning", default=None, metavar="CHUNK,WAVES_PER_BLOCK,WAVES_PER_CU",
+                    help="run the headline box with these persistent-kernel tiles instead of "
+                         "autotuning (for profiling runs of a known launch shape)")
     ap.add_argument("--print-sources-sha1", action="store_true",
                     help="print the SHA-1 of the PP kernel sources the traffic figure is tied to")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -557,7 +560,13 @@ def main():
     mass = torch.tensor(box.mass, device="cuda")
     acc = torch.empty((3, box.n), dtype=torch.float32, device="cuda")
     plan = pp.Plan(p, box.n)
-    tuning = plan.get_tuning() if args.no_tune else plan.autotune(pos, mass)   # untimed, one-off
+    if args.tuning:
+        chunk, wpb, wpc = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(chunk=chunk, persistent=1, waves_per_cu=wpc, use_graph=0, variant=0,
+                        waves_per_block=wpb)
+        tuning = plan.get_tuning()
+    else:
+        tuning = plan.get_tuning() if args.no_tune else plan.autotune(pos, mass)   # untimed, one-off
     plan.accel(pos, mass, out=acc)
     interactions = plan.count_interactions()
     for _ in range(args.warmup):

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libphoton_pp.so")
-SOURCES = ["keys_sort.hip", "tree.hip", "pp_kernels.hip", "pm.hip", "kdk.hip", "api.hip"]
+SOURCES = ["keys_sort.hip", "scan.hip", "tree.hip", "pp_kernels.hip", "pm.hip", "kdk.hip", "api.hip"]
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -55,6 +55,7 @@ int DevBuf::reserve(size_t need) {
         t_arena->used += want;
         bytes = want;
         carved = true;
+        tag = 0;
         ++g_alloc_generation;
         return PP_OK;
     }
@@ -69,6 +70,7 @@ int DevBuf::reserve(size_t need) {
         return e == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE;
     }
     bytes = want;
+    tag = 0;
     ++g_alloc_generation;
     return PP_OK;
 }
@@ -255,7 +257,6 @@ struct Batch {
         evaluated_valid = false;
         w.pos_n = N;
         PP_TRY(reset_sizes(w, s));
-        PP_HIP(hipMemsetAsync(w.bad.p, 0, sizeof(int), s));
         PP_TRY(stage_keys(bd, N, pos, w, s));
         PP_TRY(stage_sort(bd, N, w, s));
         if (mass_d) PP_TRY(w.mass_sd.reserve(8 * (N > 0 ? N : 1)));
@@ -325,8 +326,7 @@ struct Batch {
 
     int run_pp_direct(float* acc, hipStream_t s) {
         unsigned long long* ctr = counters.as<unsigned long long>();
-        PP_HIP(hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s));
-        if (tune.persistent) PP_TRY(launch_reset_queues(queues.as<unsigned>(), s));
+        PP_TRY(launch_reset_queues(tune.persistent ? queues.as<unsigned>() : nullptr, s, ctr));
         if (timing) PP_HIP(hipEventRecord(ev0, s));
         PP_TRY(launch_pp_f32(bd, w, tune.waves_per_block, tune.persistent ? Mode::kPersistent : Mode::kGrid,
                              tune.waves_per_cu, tune.variant, partial.as<float>(), acc, ctr,

@@ -11,9 +11,6 @@
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-#include <rocprim/iterator/counting_iterator.hpp>
-#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "pp_internal.h"
 
@@ -150,7 +147,6 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
     mass_s[k] = (M)r.w;
 }
 
-__global__ void set_zero_i64(int64_t* p) { *p = 0; }
 
 __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,15 +189,6 @@ __global__ void __launch_bounds__(256) gather_keys_kernel(const uint64_t* __rest
     if (k >= N) return;
     out[k] = keys[perm[k]];
 }
-
-// i -> in[i] widened, 0 past the end: an exclusive scan over n + 1 of these
-// writes the offsets and the total (off[n]) in one pass.
-struct count_at {
-    const int32_t* in;
-    int64_t n;
-    __device__ __host__ int64_t operator()(int64_t i) const { return i < n ? (int64_t)in[i] : 0; }
-};
-using count_iter = rocprim::transform_iterator<rocprim::counting_iterator<int64_t>, count_at, int64_t>;
 
 // The key sort: one-sweep radix with 10-bit digits (7 passes over 63 key
 // bits instead of 8 with the library's 8-bit default for this target).
@@ -321,35 +308,6 @@ int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* 
                            w.pos_s.as<double>(), w.mass_sd.as<double>());
     }
     PP_HIP(hipGetLastError());
-    return PP_OK;
-}
-
-int scan_workspace(int64_t n, size_t* bytes) {
-    size_t b = 0;
-    count_iter it(rocprim::counting_iterator<int64_t>(0), count_at{nullptr, n});
-    PP_HIP(rocprim::exclusive_scan((void*)nullptr, b, it, (int64_t*)nullptr, (int64_t)0,
-                                   (size_t)(n + 1), rocprim::plus<int64_t>(), (hipStream_t)0));
-    *bytes = b;
-    return PP_OK;
-}
-
-int grow_scan(DevBuf& buf, int64_t n) {
-    size_t need = 0;
-    PP_TRY(scan_workspace(n, &need));
-    return buf.reserve(need + 1);
-}
-
-int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s) {
-    if (n == 0) {
-        hipLaunchKernelGGL(set_zero_i64, dim3(1), dim3(1), 0, s, off);
-        PP_HIP(hipGetLastError());
-        return PP_OK;
-    }
-    PP_TRY(grow_scan(ws, n));
-    size_t b = ws.bytes;
-    count_iter it(rocprim::counting_iterator<int64_t>(0), count_at{in, n});
-    PP_HIP(rocprim::exclusive_scan(ws.p, b, it, off, (int64_t)0, (size_t)(n + 1),
-                                   rocprim::plus<int64_t>(), s));
     return PP_OK;
 }
 

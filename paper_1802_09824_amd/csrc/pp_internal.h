@@ -54,6 +54,7 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     bool carved = false;     // carved from an Arena (not hipMalloc'ed)
+    uint32_t tag = 0;        // free for the owner's bookkeeping; 0 after every reallocation
     int reserve(size_t need);
     void release();
     template <class T> T* as() const { return static_cast<T*>(p); }
@@ -172,7 +173,8 @@ enum SizeSlot : int {
     kChunk = 6,         // source-list positions per work item (the effective chunk)
     kSkip = 7,          // nonzero: a buffer was too small or an input not finite; the PP kernels return
     kCand = 8,          // (target, listed source) pairs
-    kOverflow = 9,      // bit 0: blocks, 1: entries, 2: ranges, 3: items, 4: a list longer than int32
+    kOverflow = 9,      // bit 0: blocks, 1: entries, 2: ranges, 3: items, 4: a list longer than int32,
+                        // 6: a single-pass scan gave up waiting
     kBad = 10,          // a non-finite position or mass
     kNeedBlock = 11,
     kNeedRange = 12,
@@ -261,10 +263,17 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);
 int stage_gather(const BatchDev& bd, int64_t N, const double* pos, const float* mass_f,
                  const double* mass_d, Work& w, hipStream_t s);
 int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes);
+// workspace bytes of a single-pass scan over n counts (scan.hip)
 int scan_workspace(int64_t n, size_t* bytes);
-int grow_scan(DevBuf& buf, int64_t n);
+// reserves the workspace for n counts; fresh memory is cleared on stream s
+int grow_scan(DevBuf& buf, int64_t n, hipStream_t s);
 // exclusive scan of int32 counts into int64 offsets; off has n + 1 entries
-int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s);
+// (off[n] = total); sizes, when given, gets overflow bit 6 if the scan gave up
+int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s,
+                           int64_t* sizes = nullptr);
+// the same for two count arrays of equal length in one pass
+int launch_scan2_i32_to_i64(const int32_t* a, const int32_t* b, int64_t* oa, int64_t* ob, int64_t n,
+                            DevBuf& ws, hipStream_t s, int64_t* sizes = nullptr);
 int launch_keys_raw(const double* pos, int64_t n, double L, int bits, uint64_t* keys,
                     hipStream_t s);
 int launch_sort_raw(const uint64_t* keys, const int32_t* idx_in, uint64_t* keys_out,
@@ -337,6 +346,6 @@ int launch_reduce_count(const BatchDev& bd, const Work& w, const int32_t* partia
                         unsigned long long* total, hipStream_t s);
 // Builds the interpolated split table (FP64 series, rounded to FP32).
 int launch_split_table(Work& w, hipStream_t s);
-int launch_reset_queues(unsigned* queues, hipStream_t s);
+int launch_reset_queues(unsigned* queues, hipStream_t s, unsigned long long* counters = nullptr);
 
 }  // namespace pp

@@ -154,8 +154,7 @@ __device__ __forceinline__ void pair_f32(const float4 sj, float xi, float yi, fl
     float y = __builtin_amdgcn_rsqf(r2);
     if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
     const float h = split_h<TABLE>(r2, tab);
-    const float y3 = y * y * y;
-    float F = (y3 - h) * sj.w;
+    float F = fmaf(y * y, y, -h) * sj.w;
     F = r2 < P.cut2 ? F : 0.f;
     tx = fmaf(F, dx, tx);
     ty = fmaf(F, dy, ty);
@@ -176,8 +175,7 @@ __device__ __forceinline__ void pair_f32_eq(const float4 sj, float xi, float yi,
     float y = __builtin_amdgcn_rsqf(r2);
     if (NEWTON) y = y * fmaf(-0.5f * r2 * y, y, 1.5f);
     const float h = split_h<TABLE>(r2, tab);
-    const float y3 = y * y * y;
-    float F = y3 - h;
+    float F = fmaf(y * y, y, -h);
     F = r2 < sj.w ? F : 0.f;
     tx = fmaf(F, dx, tx);
     ty = fmaf(F, dy, ty);
@@ -666,8 +664,10 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
     }
 }
 
-__global__ void reset_queues_kernel(unsigned* q) {
-    if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+// Clears the work queues and (when given) the three kernel counters.
+__global__ void reset_queues_kernel(unsigned* q, unsigned long long* ctr) {
+    if (q && threadIdx.x < 8) q[threadIdx.x] = 0u;
+    if (ctr && threadIdx.x < 3) ctr[threadIdx.x] = 0ull;
 }
 
 // One thread per (block, lane), grid-stride: sum the item partials of the
@@ -906,8 +906,8 @@ int launch_split_table(Work& w, hipStream_t s) {
     return PP_OK;
 }
 
-int launch_reset_queues(unsigned* queues, hipStream_t s) {
-    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, queues);
+int launch_reset_queues(unsigned* queues, hipStream_t s, unsigned long long* counters) {
+    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, queues, counters);
     PP_HIP(hipGetLastError());
     return PP_OK;
 }

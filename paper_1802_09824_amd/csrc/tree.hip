@@ -736,50 +736,31 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
 // Depth-first walk of one entry's subtree (at most 8^2 = 64 leaves).  The
 // count pass records which leaves of the subtree pass as a 64-bit mask
 // (bit = leaf - first leaf of the subtree); the fill pass turns the mask
-// back into runs without testing boxes again.  Inside entries and leaf
-// entries are a single run and need no mask.
+// back into runs without testing boxes again, writing them from range slot
+// o and list position pos.  Inside entries and leaf entries are a single
+// run and need no mask.  Returns the entry's runs (nr) and sources (tot);
+// with monopole acceptance on (count pass), children met by the walk are
+// tested too: accepted leaves go to m0 (bit = leaf - first leaf of the
+// entry), accepted groups of 8 leaves to m1 (bit = group - first group),
+// and are not listed.
 template <bool FILL>
-__global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
-                              const IBox* __restrict__ nodes, const FEntry* __restrict__ ent,
-                              int64_t F, const IBox* __restrict__ bbox,
-                              const int32_t* __restrict__ bboxid,
-                              const int64_t* __restrict__ leaf_begin,
-                              const int32_t* __restrict__ leaf_count, uint64_t* __restrict__ lmask,
-                              int32_t* __restrict__ rcnt, int32_t* __restrict__ scnt,
-                              const int64_t* __restrict__ roff, const int64_t* __restrict__ soff,
-                              const int64_t* __restrict__ eoff, int32_t* __restrict__ rbeg,
-                              int32_t* __restrict__ rpre, uint8_t* __restrict__ rcode,
-                              MonoDev mono, uint64_t* __restrict__ mono0,
-                              uint8_t* __restrict__ mono1, const int64_t* __restrict__ sizes,
-                              int64_t cap_range) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= F) return;                       // F: the capacity of the entry buffer
-    if (e >= sizes[kNEntry]) {
-        if (!FILL) {
-            rcnt[e] = 0;
-            scnt[e] = 0;
-            if (mono0) {
-                mono0[e] = 0;
-                mono1[e] = 0;
-            }
-        }
-        return;
-    }
-    const FEntry E = ent[e];
+__device__ void entry_ranges(const BatchDev& bd, const TreeView* __restrict__ tvs,
+                             const IBox* __restrict__ nodes, const FEntry E, int64_t e,
+                             const IBox* __restrict__ bbox, const int32_t* __restrict__ bboxid,
+                             const int64_t* __restrict__ leaf_begin,
+                             const int32_t* __restrict__ leaf_count, uint64_t* __restrict__ lmask,
+                             int32_t* __restrict__ rbeg, int32_t* __restrict__ rpre,
+                             uint8_t* __restrict__ rcode, const MonoDev& mono, int64_t o,
+                             int64_t pos, int64_t cap_range, int32_t& nr, int64_t& tot,
+                             uint64_t& m0, uint32_t& m1) {
     const int x = bboxid[E.blk];
     const TreeView& tv = tvs[x];
     const int64_t nleaf = tv.cnt[0];
-    // with monopole acceptance on (count pass), children met by the walk are
-    // tested too: accepted leaves go to mono0 (bit = leaf - first leaf of the
-    // entry), accepted groups of 8 leaves to mono1 (bit = group - first
-    // group), and are not listed
     const bool mono_on = !FILL && (mono.theta2 > 0.0 || mono.alpha > 0.0);
-    uint64_t m0 = 0;
-    uint32_t m1 = 0;
-    int64_t o = FILL ? roff[e] : 0;
-    int64_t pos = FILL ? soff[e] - soff[eoff[E.blk]] : 0;
-    int32_t nr = 0;
-    int64_t tot = 0;
+    m0 = 0;
+    m1 = 0;
+    nr = 0;
+    tot = 0;
     // one run of local leaves [l0, l1]
     auto emit = [&](int64_t l0, int64_t l1) {
         const int64_t p0 = leaf_begin[tv.loff + l0];
@@ -865,29 +846,35 @@ __global__ void ranges_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
             mask = z >= 64 ? 0ull : mask & (~0ull << z);
         }
     }
-    if (!FILL) {
-        rcnt[e] = nr;
-        scnt[e] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
-        if (mono0) {
-            mono0[e] = m0;
-            mono1[e] = (uint8_t)m1;
-        }
-    }
 }
 
-// First entry of every block (entries are sorted by block).
-__global__ void block_entry_kernel(const FEntry* __restrict__ ent, const int64_t* __restrict__ sizes,
-                                   int64_t cap_block, int64_t* __restrict__ eoff) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nblock = sizes[kNBlock], F = sizes[kNEntry];
-    if (b > nblock || b > cap_block) return;
-    int64_t lo = 0, hi = F;             // first e with ent[e].blk >= b
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ent[mid].blk < b) lo = mid + 1;
-        else hi = mid;
+// Count pass: every entry walks its subtree and records its runs (rcnt)
+// and listed sources (scnt); entries past the entry count get zero.
+__global__ void ranges_count_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
+                                    const IBox* __restrict__ nodes, const FEntry* __restrict__ ent,
+                                    int64_t F, const IBox* __restrict__ bbox,
+                                    const int32_t* __restrict__ bboxid,
+                                    const int64_t* __restrict__ leaf_begin,
+                                    const int32_t* __restrict__ leaf_count,
+                                    uint64_t* __restrict__ lmask, int32_t* __restrict__ rcnt,
+                                    int32_t* __restrict__ scnt, MonoDev mono,
+                                    uint64_t* __restrict__ mono0, uint8_t* __restrict__ mono1,
+                                    const int64_t* __restrict__ sizes) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= F) return;                       // F: the capacity of the entry buffer
+    int32_t nr = 0;
+    int64_t tot = 0;
+    uint64_t m0 = 0;
+    uint32_t m1 = 0;
+    if (e < sizes[kNEntry])
+        entry_ranges<false>(bd, tvs, nodes, ent[e], e, bbox, bboxid, leaf_begin, leaf_count, lmask,
+                            nullptr, nullptr, nullptr, mono, 0, 0, 0, nr, tot, m0, m1);
+    rcnt[e] = nr;
+    scnt[e] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
+    if (mono0) {
+        mono0[e] = m0;
+        mono1[e] = (uint8_t)m1;
     }
-    eoff[b] = lo;
 }
 
 // Per-block range offsets and list lengths; flags a list longer than int32.
@@ -903,6 +890,45 @@ __global__ void block_sum_kernel(const int64_t* __restrict__ eoff, const int64_t
     const int64_t len = soff_e[eoff[b + 1]] - soff_e[eoff[b]];
     if (len > INT32_MAX) atomicOr(reinterpret_cast<unsigned long long*>(sizes + kOverflow), 16ull);
     slen[b] = (int32_t)(len < INT32_MAX ? len : INT32_MAX);
+}
+
+// Fill pass: every entry writes its runs from its first range slot, with
+// list positions relative to its block.
+__global__ void ranges_fill_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
+                                   const IBox* __restrict__ nodes, const FEntry* __restrict__ ent,
+                                   int64_t F, const IBox* __restrict__ bbox,
+                                   const int32_t* __restrict__ bboxid,
+                                   const int64_t* __restrict__ leaf_begin,
+                                   const int32_t* __restrict__ leaf_count,
+                                   uint64_t* __restrict__ lmask, const int64_t* __restrict__ roff_e,
+                                   const int64_t* __restrict__ soff_e, const int64_t* __restrict__ eoff,
+                                   int32_t* __restrict__ rbeg, int32_t* __restrict__ rpre,
+                                   uint8_t* __restrict__ rcode, MonoDev mono,
+                                   const int64_t* __restrict__ sizes, int64_t cap_range) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= F || e >= sizes[kNEntry]) return;    // F: the capacity of the entry buffer
+    const FEntry E = ent[e];
+    int32_t nr;
+    int64_t tot;
+    uint64_t m0;
+    uint32_t m1;
+    entry_ranges<true>(bd, tvs, nodes, E, e, bbox, bboxid, leaf_begin, leaf_count, lmask, rbeg, rpre,
+                       rcode, mono, roff_e[e], soff_e[e] - soff_e[eoff[E.blk]], cap_range, nr, tot, m0, m1);
+}
+
+// First entry of every block (entries are sorted by block).
+__global__ void block_entry_kernel(const FEntry* __restrict__ ent, const int64_t* __restrict__ sizes,
+                                   int64_t cap_block, int64_t* __restrict__ eoff) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nblock = sizes[kNBlock], F = sizes[kNEntry];
+    if (b > nblock || b > cap_block) return;
+    int64_t lo = 0, hi = F;             // first e with ent[e].blk >= b
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ent[mid].blk < b) lo = mid + 1;
+        else hi = mid;
+    }
+    eoff[b] = lo;
 }
 
 // Listed sources in all (sum of the block list lengths) and the effective
@@ -993,8 +1019,9 @@ __global__ void finish_sizes_kernel(int64_t* __restrict__ sizes, const int64_t* 
     sizes[kSkip] = (sizes[kOverflow] != 0 || sizes[kBad] != 0) ? 1 : 0;
 }
 
-__global__ void zero_sizes_kernel(int64_t* __restrict__ sizes) {
+__global__ void zero_sizes_kernel(int64_t* __restrict__ sizes, int* __restrict__ bad) {
     if (threadIdx.x < kSizeSlots) sizes[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *bad = 0;
 }
 
 }  // namespace
@@ -1023,9 +1050,12 @@ static int levels_for(int64_t n) {
     return h;
 }
 
+// Clears the count slots and the bad-input flag.
 int reset_sizes(Work& w, hipStream_t s) {
     PP_TRY(w.sizes.reserve(sizeof(int64_t) * kSizeSlots));
-    hipLaunchKernelGGL(zero_sizes_kernel, dim3(1), dim3(kSizeSlots), 0, s, w.sizes.as<int64_t>());
+    PP_TRY(w.bad.reserve(64));
+    hipLaunchKernelGGL(zero_sizes_kernel, dim3(1), dim3(kSizeSlots), 0, s, w.sizes.as<int64_t>(),
+                       w.bad.as<int>());
     PP_HIP(hipGetLastError());
     return PP_OK;
 }
@@ -1062,7 +1092,7 @@ int stage_leaves(const BatchDev& bd, int64_t N, const uint64_t* sorted_keys, con
                            w.level_p.as<int8_t>(), N, w.flag.as<int32_t>());
         PP_HIP(hipGetLastError());
     }
-    PP_TRY(launch_scan_i32_to_i64(w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N, w.scan_ws, s));
+    PP_TRY(launch_scan_i32_to_i64(w.flag.as<int32_t>(), w.flag_off.as<int64_t>(), N, w.scan_ws, s, w.sizes.as<int64_t>()));
     hipLaunchKernelGGL(leaf_offsets_kernel, dim3(blocks_for(bd.nbox + 1, 64)), dim3(64), 0, s, bd,
                        w.flag_off.as<int64_t>(), w.loff_dev.as<int64_t>(), w.sizes.as<int64_t>());
     PP_HIP(hipGetLastError());
@@ -1230,7 +1260,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     for (int p = 0; p < npass; ++p) capcnt = w.cap_ent[p] > capcnt ? w.cap_ent[p] : capcnt;
     // the scans' workspace for the largest scan of the pass, reserved before
     // the first one is enqueued
-    PP_TRY(grow_scan(w.scan_ws, capcnt > nc ? capcnt : nc));
+    PP_TRY(grow_scan(w.scan_ws, 2 * (capcnt > nc ? capcnt : nc), s));
     const double* pos_s = w.pos_s.as<double>();
     if (nc > 0) {
         hipLaunchKernelGGL(block_split_kernel<false>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
@@ -1239,7 +1269,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                            (IBox*)nullptr, (int32_t*)nullptr, cb);
         PP_HIP(hipGetLastError());
     }
-    PP_TRY(launch_scan_i32_to_i64(w.ccount.as<int32_t>(), w.coff.as<int64_t>(), nc, w.scan_ws, s));
+    PP_TRY(launch_scan_i32_to_i64(w.ccount.as<int32_t>(), w.coff.as<int64_t>(), nc, w.scan_ws, s, sizes));
     hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.coff.as<int64_t>() + nc,
                        (int)kNBlock, (int)kNeedBlock, cb, 1ull);
     if (nc > 0)
@@ -1280,7 +1310,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                        nodes, bbox, bboxid, (const int64_t*)sizes, cb, w.fcnt.as<int32_t>(),
                        (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
     PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cb, w.scan_ws, s));
+    PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cb, w.scan_ws, s, sizes));
     hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cb,
                        (int)kEntry0, (int)kNeedEntry0, w.cap_ent[0], 2ull);
     hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(cb, 128)), dim3(128), 0, s, bd, tvs,
@@ -1297,7 +1327,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                            (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, w.fcnt.as<int32_t>(),
                            (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
         PP_HIP(hipGetLastError());
-        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cin, w.scan_ws, s));
+        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cin, w.scan_ws, s, sizes));
         hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cin,
                            (int)(kEntry0 + p), (int)(kNeedEntry0 + p), cout, 2ull);
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd, tvs,
@@ -1334,40 +1364,39 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     w.mono1 = mono1;
     if (w.cap_range < 1024) w.cap_range = 16 * cb;
     if (w.cap_item < 1024) w.cap_item = 2 * cb;
-    hipLaunchKernelGGL(ranges_kernel<false>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
-                       nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
-                       w.rcnt_e.as<int32_t>(), w.scnt_e.as<int32_t>(), (const int64_t*)nullptr,
-                       (const int64_t*)nullptr, (const int64_t*)nullptr, (int32_t*)nullptr,
-                       (int32_t*)nullptr, (uint8_t*)nullptr, mono, mono0, mono1,
-                       (const int64_t*)sizes, w.cap_range);
+    hipLaunchKernelGGL(ranges_count_kernel, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs, nodes, ent,
+                       F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(), w.rcnt_e.as<int32_t>(),
+                       w.scnt_e.as<int32_t>(), mono, mono0, mono1, (const int64_t*)sizes);
+    PP_HIP(hipGetLastError());
+    PP_TRY(launch_scan2_i32_to_i64(w.rcnt_e.as<int32_t>(), w.scnt_e.as<int32_t>(), w.roff_e.as<int64_t>(),
+                                   w.soff_e.as<int64_t>(), F, w.scan_ws, s, sizes));
     hipLaunchKernelGGL(block_entry_kernel, dim3(blocks_for(cb + 1, 256)), dim3(256), 0, s, ent,
                        (const int64_t*)sizes, cb, w.eoff.as<int64_t>());
-    PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.rcnt_e.as<int32_t>(), w.roff_e.as<int64_t>(), F, w.scan_ws, s));
-    PP_TRY(launch_scan_i32_to_i64(w.scnt_e.as<int32_t>(), w.soff_e.as<int64_t>(), F, w.scan_ws, s));
     hipLaunchKernelGGL(block_sum_kernel, dim3(blocks_for(cb + 1, 256)), dim3(256), 0, s,
-                       w.eoff.as<int64_t>(), w.roff_e.as<int64_t>(), w.soff_e.as<int64_t>(), sizes, cb,
-                       w.roff.as<int64_t>(), w.slen.as<int32_t>());
+                       (const int64_t*)w.eoff.as<int64_t>(), (const int64_t*)w.roff_e.as<int64_t>(),
+                       (const int64_t*)w.soff_e.as<int64_t>(), sizes, cb, w.roff.as<int64_t>(),
+                       w.slen.as<int32_t>());
+    PP_HIP(hipGetLastError());
     constexpr int64_t kMaxItems = 1 << 21;
-    hipLaunchKernelGGL(chunk_kernel, dim3(1), dim3(1), 0, s, w.soff_e.as<int64_t>(), sizes,
+    hipLaunchKernelGGL(chunk_kernel, dim3(1), dim3(1), 0, s, (const int64_t*)w.soff_e.as<int64_t>(), sizes,
                        (int64_t)chunk_req, kMaxItems);
     w.active = active;
     hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
                        w.slen.as<int32_t>(), w.bcount.as<int32_t>(), sizes, cb, active,
                        w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>());
     PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), cb, w.scan_ws, s));
+    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), cb, w.scan_ws, s, sizes));
     PP_TRY(w.rbeg.reserve(sizeof(int32_t) * (w.cap_range + 1)));
     PP_TRY(w.rpre.reserve(sizeof(int32_t) * (w.cap_range + 1)));
     PP_TRY(w.rcode.reserve(sizeof(uint8_t) * (w.cap_range + 1)));
     PP_TRY(w.iblock.reserve(sizeof(int32_t) * (w.cap_item + 1)));
     PP_TRY(w.is0.reserve(sizeof(int32_t) * (w.cap_item + 1)));
-    hipLaunchKernelGGL(ranges_kernel<true>, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs,
-                       nodes, ent, F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
-                       (int32_t*)nullptr, (int32_t*)nullptr, w.roff_e.as<int64_t>(),
-                       w.soff_e.as<int64_t>(), w.eoff.as<int64_t>(), w.rbeg.as<int32_t>(),
-                       w.rpre.as<int32_t>(), w.rcode.as<uint8_t>(), mono, (uint64_t*)nullptr,
-                       (uint8_t*)nullptr, (const int64_t*)sizes, w.cap_range);
+    hipLaunchKernelGGL(ranges_fill_kernel, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs, nodes, ent,
+                       F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
+                       (const int64_t*)w.roff_e.as<int64_t>(), (const int64_t*)w.soff_e.as<int64_t>(),
+                       (const int64_t*)w.eoff.as<int64_t>(), w.rbeg.as<int32_t>(), w.rpre.as<int32_t>(),
+                       w.rcode.as<uint8_t>(), mono, (const int64_t*)sizes, w.cap_range);
+    PP_HIP(hipGetLastError());
     hipLaunchKernelGGL(item_fill_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
                        w.icount.as<int32_t>(), w.ioff.as<int64_t>(), (const int64_t*)sizes, w.cap_item,
                        w.iblock.as<int32_t>(), w.is0.as<int32_t>());
@@ -1384,6 +1413,7 @@ int lists_to_host(Work& w, hipStream_t s, bool* regrow) {
     PP_HIP(hipMemcpyAsync(h, w.sizes.p, sizeof(int64_t) * kSizeSlots, hipMemcpyDeviceToHost, s));
     PP_HIP(hipStreamSynchronize(s));
     if (h[kBad]) return fail(PP_EINVAL, "non-finite position or mass");
+    if (h[kOverflow] & 64) return fail(PP_EDEVICE, "the list builder's single-pass scan did not complete");
     if (h[kOverflow] & 16) return fail(PP_ERANGE, "a target block lists more than 2^31 sources");
     if (h[kOverflow]) {
         w.cap_block = grow_cap(w.cap_block, h[kNeedBlock]);
