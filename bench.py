@@ -254,11 +254,13 @@ def bench_monopoles(plan, box, pos, mass, theta=0.3, alpha=0.005, steps=3):
                                "p999": nearest_rank(e, 99.9), "max": float(e.max())}}
 
 
-def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, steps=2):
+def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, steps=2, skin=0.0):
     """Adaptive block-step KDK over the whole force (PP + PM) on the same box:
     the top step is twice the median particle's step criterion, so the
     particles spread over several levels; sub-steps evaluate the short-range
-    force for the particles whose step ends only."""
+    force for the particles whose step ends only.  skin > 0: the sub-steps
+    reuse the short-range lists (built with the cut widened by skin) while
+    no particle has moved skin / 2."""
     import numpy as np
     import torch
     import paper_1802_09824_amd as pp
@@ -268,6 +270,7 @@ def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, ste
     rng = np.random.default_rng(3)
     V = torch.tensor(rng.normal(scale=1e-3, size=(3, box.n)), device="cuda")
     K = pp.KDK(box.params, box.n, n_mesh=n_mesh, eta=eta, max_level=max_level)
+    K.set_skin(skin)
     K.init(P, mass)
     K.step(P, V, mass, dt)
     torch.cuda.synchronize()
@@ -280,9 +283,10 @@ def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, ste
     i1 = K.info()
     evals = (i1["force_evaluations"] - i0["force_evaluations"]) / steps
     targets = (i1["short_range_targets"] - i0["short_range_targets"]) / steps
+    builds = (i1["list_builds"] - i0["list_builds"]) / steps
     del K
-    return {"n_mesh": n_mesh, "eta": eta, "dt": dt, "ms_per_top_step": 1e3 * sec,
-            "force_evaluations_per_top_step": evals,
+    return {"n_mesh": n_mesh, "eta": eta, "dt": dt, "skin": skin, "ms_per_top_step": 1e3 * sec,
+            "force_evaluations_per_top_step": evals, "list_builds_per_top_step": builds,
             "short_range_targets_per_top_step": targets,
             "fraction_of_full_short_range": targets / (evals * box.n),
             "level_count": i1["level_count"][:max_level + 1]}
@@ -636,7 +640,12 @@ def main():
                                     with_error=not args.no_cpu_baseline)
     if not args.no_extras:
         out["monopoles"] = bench_monopoles(plan, box, pos, mass)
-        out["kdk_adaptive"] = bench_kdk(box, pos, mass, acc)
+        kdk = bench_kdk(box, pos, mass, acc)
+        reuse = bench_kdk(box, pos, mass, acc, skin=0.05 * box.params.rcut)
+        kdk["list_reuse"] = {k: reuse[k] for k in ("skin", "ms_per_top_step", "list_builds_per_top_step",
+                                                   "force_evaluations_per_top_step")}
+        kdk["list_reuse"]["speedup"] = kdk["ms_per_top_step"] / reuse["ms_per_top_step"]
+        out["kdk_adaptive"] = kdk
         out["small_box"] = bench_small_box()
     del plan, pos, mass, acc
     torch.cuda.empty_cache()

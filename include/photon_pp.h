@@ -200,6 +200,8 @@ typedef struct pp_stats {
                                monopole acceptance on (0 when off, -1 if unknown) */
     double pp_stage_ms;     /* the whole PP stage of that call (queue reset, kernel or
                                graph, reduction, monopoles) when timing is on, else -1 */
+    int64_t list_builds;    /* FP32 calls (pp_accel, pp_accel_active) that built the lists */
+    int64_t list_reuses;    /* FP32 calls that reused them (pp_plan_set_skin) */
 } pp_stats;
 /* Waits for the last PP kernel when timing is on.                          */
 /* Monopole acceptance (sec. 3.3, the 1-to-N case of the dual tree walk) for
@@ -229,6 +231,22 @@ int pp_plan_set_monopole(pp_plan* plan, double theta);
  * outside 1..the plan's capacity. */
 int pp_plan_set_monopole_relative(pp_plan* plan, double alpha, const float* acc_ref, int64_t n,
                                   void* stream);
+/* List reuse between calls on moving particles (for a time integrator's
+ * substeps, sec. 3.4).  With skin > 0 the near lists are built with the cut
+ * widened to rcut + skin (a length), and a later pp_accel or pp_accel_active
+ * on the plan reuses them, without keys, sort, leaves or lists, while every
+ * particle (same index in the input arrays) lies within skin / 2 of its
+ * position at the last build (minimum image): no pair within rcut can then
+ * be missing from them, and the pair test still uses rcut, so the forces are
+ * those of a fresh build up to FP32 summation order.  A call that finds a
+ * particle further away rebuilds the lists (one extra pass) and makes the
+ * new positions the reference.  Reuse needs monopole acceptance off and a
+ * kernel variant that prunes sources against the targets' current positions
+ * (variants with bit 2 clear, the default included); otherwise every call
+ * builds.  pp_count_interactions refuses lists reused for moved particles.
+ * skin = 0 (the default) builds on every call.  Errors: PP_EINVAL for a
+ * negative or non-finite skin, PP_ERANGE when rcut + skin >= L / 2. */
+int pp_plan_set_skin(pp_plan* plan, double skin);
 int pp_plan_stats(pp_plan* plan, pp_stats* out);
 
 /* Turn HIP-event timing of the PP kernel on (1) or off (0).  With graph
@@ -396,6 +414,9 @@ void pp_pm_plan_destroy(pp_pm_plan* plan);
  *   in place), vel (FP64 [3][n], updated in place) with masses mass (FP32
  *   [n]); device pointers; enqueued on the stream.  Synchronises the stream
  *   once per step to read the level histogram.
+ * pp_kdk_set_skin: pp_plan_set_skin on the object's PP plan: the substeps
+ *   then reuse the short-range lists while no particle has moved skin / 2
+ *   since they were built (0, the default: a build per force evaluation).
  * pp_kdk_get_info: counters of the object.
  * pp_kdk_levels: copies the levels of the last step (int8 [n], device).
  * pp_kdk_accel: copies the current forces (FP32 [3][n] short range, then
@@ -408,11 +429,14 @@ typedef struct pp_kdk_info {
     int64_t level_count[16];     /* particles per level in the last top step */
     int64_t short_range_targets; /* targets given new short-range forces, summed
                                     over the force evaluations */
+    int64_t list_builds;         /* force evaluations that built the short-range
+                                    lists (the others reused them) */
 } pp_kdk_info;
 int pp_kdk_create(const pp_box_params* p, int32_t n_mesh, int64_t n, double eta, int32_t max_level,
                   pp_kdk** out);
 int pp_kdk_init(pp_kdk* k, const double* pos, const float* mass, void* stream);
 int pp_kdk_step(pp_kdk* k, double* pos, double* vel, const float* mass, double dt, void* stream);
+int pp_kdk_set_skin(pp_kdk* k, double skin);
 int pp_kdk_get_info(const pp_kdk* k, pp_kdk_info* out);
 int pp_kdk_levels(const pp_kdk* k, int8_t* level, void* stream);
 int pp_kdk_accel(const pp_kdk* k, float* acc, void* stream);

@@ -49,7 +49,8 @@ class pp_stats(C.Structure):
                 ("nrange", C.c_int64), ("nitem", C.c_int64), ("candidates", C.c_int64),
                 ("evaluated", C.c_int64), ("lane_pairs", C.c_int64),
                 ("interactions", C.c_int64), ("pp_kernel_ms", C.c_double),
-                ("monopoles", C.c_int64), ("pp_stage_ms", C.c_double)]
+                ("monopoles", C.c_int64), ("pp_stage_ms", C.c_double),
+                ("list_builds", C.c_int64), ("list_reuses", C.c_int64)]
 
 
 _P, _i64, _i32, _dbl, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_size_t
@@ -74,6 +75,8 @@ _SIGS = {
     "pp_accel_scratch": (_i32, [C.POINTER(pp_box_params), _P, _P, _i64, _P, _P]),
     "pp_plan_stats": (_i32, [_P, C.POINTER(pp_stats)]),
     "pp_plan_set_monopole": (_i32, [_P, C.c_double]),
+    "pp_plan_set_skin": (_i32, [_P, C.c_double]),
+    "pp_kdk_set_skin": (_i32, [_P, C.c_double]),
     "pp_accel_active": (_i32, [_P, _P, _P, _i64, _P, _P, _P]),
     "pp_plan_set_monopole_relative": (_i32, [_P, C.c_double, _P, _i64, _P]),
     "pp_count_interactions": (_i32, [_P, _P, C.POINTER(_i64), _P]),
@@ -287,6 +290,11 @@ class Plan:
         """Monopole acceptance for accel (0 = exact pair sums)."""
         _check(_lib.pp_plan_set_monopole(self._h, float(theta)), "pp_plan_set_monopole")
 
+    def set_skin(self, skin: float):
+        """Lists built with the cut widened by skin are reused by later accel
+        calls while every particle stays within skin / 2 (0 = build every call)."""
+        _check(_lib.pp_plan_set_skin(self._h, float(skin)), "pp_plan_set_skin")
+
     def set_monopole_relative(self, alpha: float, acc_ref: torch.Tensor | None = None, stream=None):
         """Gadget-2's relative opening test for accel against reference
         accelerations acc_ref [3][n] (FP32, device); alpha = 0 turns it off."""
@@ -481,7 +489,7 @@ def pp_pm_plan_create(params, n_mesh: int) -> PMPlan:
 class pp_kdk_info(C.Structure):
     _fields_ = [("deepest_level", C.c_int32), ("pad", C.c_int32), ("top_steps", C.c_int64),
                 ("force_evaluations", C.c_int64), ("level_count", C.c_int64 * 16),
-                ("short_range_targets", C.c_int64)]
+                ("short_range_targets", C.c_int64), ("list_builds", C.c_int64)]
 
 
 class KDK:
@@ -512,7 +520,11 @@ class KDK:
         _check(_lib.pp_kdk_get_info(self._h, C.byref(i)), "pp_kdk_get_info")
         return {"deepest_level": i.deepest_level, "top_steps": i.top_steps,
                 "force_evaluations": i.force_evaluations, "level_count": list(i.level_count),
-                "short_range_targets": i.short_range_targets}
+                "short_range_targets": i.short_range_targets, "list_builds": i.list_builds}
+
+    def set_skin(self, skin: float):
+        """Reuse the short-range lists across substeps (pp_kdk_set_skin)."""
+        _check(_lib.pp_kdk_set_skin(self._h, float(skin)), "pp_kdk_set_skin")
 
     def levels(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n, dtype=torch.int8, device="cuda")

@@ -114,7 +114,7 @@ int HostBuf::reserve(size_t need) {
 
 HostBuf::~HostBuf() { host_free(*this); }
 
-BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
+BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n, double skin) {
     BoxDev b{};
     b.L = p.L;
     b.qscale = ldexp(1.0, p.key_bits) / p.L;
@@ -127,7 +127,7 @@ BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n) {
     b.eps = p.eps;
     b.G = p.G;
     b.W = (int64_t)1 << p.key_bits;
-    const double r = p.rcut * ldexp(1.0, p.key_bits) / p.L;
+    const double r = (p.rcut + skin) * ldexp(1.0, p.key_bits) / p.L;
     b.T = (int64_t)ceil(r * r);
     b.emax = (int64_t)floor(2.0 * p.rcut * (double)b.W / p.L);
     b.poff = poff;
@@ -173,6 +173,14 @@ struct Batch {
     double alpha = 0.0;            // relative monopole acceptance (0: off)
     DevBuf acc_ref;                // FP32 [3][acc_ref_n]: its reference accelerations
     int64_t acc_ref_n = 0;
+    // lists built with the cut widened by `skin` are reused by later FP32
+    // calls while every particle stays within skin / 2 of pos_ref (its
+    // position, key order, when they were built)
+    double skin = 0.0;
+    DevBuf pos_ref;
+    bool reuse_ready = false;      // the lists and pos_ref belong together
+    bool lists_moved = false;      // the last pass reused the lists for moved particles
+    int64_t list_builds = 0, list_reuses = 0;
     bool lists_mono = false;       // the current lists hold monopoles
     bool lists_active = false;     // the current items cover the active targets only
     pp_stats st{};
@@ -223,11 +231,9 @@ struct Batch {
         N = poff[nb];
         n_max = N;
         if (N > INT32_MAX - 4096) return fail(PP_EINVAL, "too many particles (int32 indices)");
-        std::vector<BoxDev> hb(nb);
-        for (int x = 0; x < nb; ++x) hb[x] = make_boxdev(p[x], poff[x], n[x]);
         PP_TRY(box_dev.reserve(sizeof(BoxDev) * nb));
         PP_TRY(poff_dev.reserve(sizeof(int64_t) * (nb + 1)));
-        PP_HIP(hipMemcpy(box_dev.p, hb.data(), sizeof(BoxDev) * nb, hipMemcpyHostToDevice));
+        PP_TRY(upload_boxes());
         PP_HIP(hipMemcpy(poff_dev.p, poff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
         bd.box = box_dev.as<BoxDev>();
         bd.poff = poff_dev.as<int64_t>();
@@ -248,6 +254,33 @@ struct Batch {
         return PP_OK;
     }
 
+    // The per-box constants, with the lists' cut widened by the skin.
+    int upload_boxes() {
+        std::vector<BoxDev> hb(nbox);
+        for (int x = 0; x < nbox; ++x) hb[x] = make_boxdev(params[x], poff[x], poff[x + 1] - poff[x], skin);
+        PP_HIP(hipMemcpy(box_dev.p, hb.data(), sizeof(BoxDev) * nbox, hipMemcpyHostToDevice));
+        return PP_OK;
+    }
+
+    int set_skin(double sk) {
+        if (!(std::isfinite(sk) && sk >= 0.0)) return fail(PP_EINVAL, "skin must be finite and >= 0");
+        for (int x = 0; x < nbox; ++x)
+            if (!(params[x].rcut + sk < 0.5 * params[x].L))
+                return fail(PP_ERANGE, "rcut + skin must be < L/2");
+        skin = sk;
+        PP_TRY(upload_boxes());
+        lists_valid = false;
+        reuse_ready = false;
+        return PP_OK;
+    }
+
+    // Reuse applies to the FP32 path without monopoles, with a kernel variant
+    // whose source pruning uses the targets' current positions (not the
+    // block boxes of the build).
+    bool can_reuse() const {
+        return skin > 0.0 && reuse_ready && (tune.variant & 4) == 0 && theta == 0.0 && alpha == 0.0;
+    }
+
     // Stages shared by every entry point: keys, sort, gather, leaves, trees,
     // block lists.  Nothing is read back: the counts stay on the device until
     // finish() (see lists_to_host).
@@ -255,6 +288,8 @@ struct Batch {
                 const uint8_t* active = nullptr) {
         lists_valid = false;
         evaluated_valid = false;
+        reuse_ready = false;
+        lists_moved = false;
         w.pos_n = N;
         PP_TRY(reset_sizes(w, s));
         PP_TRY(stage_keys(bd, N, pos, w, s));
@@ -289,9 +324,26 @@ struct Batch {
         return PP_OK;
     }
 
+    // A pass that reuses the lists: the new positions and masses in the
+    // stored key order, the equal-mass flags and the work items for the
+    // given active flags; nothing else is rebuilt.
+    int prepare_reuse(const double* pos, const float* mass, hipStream_t s, const uint8_t* active) {
+        lists_valid = false;
+        evaluated_valid = false;
+        PP_TRY(reset_sizes_reuse(w, s));
+        PP_TRY(stage_regather(bd, N, pos, mass, pos_ref.as<double>(), 0.5 * skin, w, s));
+        PP_TRY(stage_mass_flags(bd, N, w, s));
+        PP_TRY(stage_items(bd, w, s, active));
+        lists_mono = false;
+        lists_active = active != nullptr;
+        lists_moved = true;
+        return PP_OK;
+    }
+
     // The end of a pass: reads the counts back (one synchronisation).  With
-    // *again set, a buffer was too small (the PP kernels did nothing) and the
-    // pass must run again with the grown capacities.
+    // *again set, a buffer was too small or a reusing pass met a particle
+    // that moved too far (the PP kernels did nothing), and the pass must run
+    // again, with the grown capacities or rebuilt lists.
     int finish(hipStream_t s, bool* again) {
         PP_TRY(lists_to_host(w, s, again));
         if (*again) {
@@ -315,11 +367,28 @@ struct Batch {
     int accel_f32(const double* pos, const float* mass, float* acc, hipStream_t s,
                   const uint8_t* active = nullptr) {
         for (int attempt = 0; attempt < 32; ++attempt) {
-            PP_TRY(prepare(pos, mass, nullptr, s, active));
+            const bool reuse = can_reuse();
+            if (reuse) PP_TRY(prepare_reuse(pos, mass, s, active));
+            else PP_TRY(prepare(pos, mass, nullptr, s, active));
             PP_TRY(run_f32(acc, s));
             bool again = false;
             PP_TRY(finish(s, &again));
-            if (!again) return PP_OK;
+            if (again) {
+                reuse_ready = false;            // rebuild (and regrow) next
+                continue;
+            }
+            if (reuse) {
+                ++list_reuses;
+            } else {
+                ++list_builds;
+                if (skin > 0.0 && !lists_mono) {
+                    // the reference positions of the reuse test
+                    PP_TRY(pos_ref.reserve(sizeof(double) * 3 * (N > 0 ? N : 1)));
+                    PP_HIP(hipMemcpyAsync(pos_ref.p, w.pos_s.p, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
+                    reuse_ready = true;
+                }
+            }
+            return PP_OK;
         }
         return fail(PP_ENOMEM, "the list buffers kept growing");
     }
@@ -418,6 +487,8 @@ struct Batch {
         }
         st.evaluated = st.lane_pairs = -1;
         st.monopoles = lists_mono ? -1 : 0;
+        st.list_builds = list_builds;
+        st.list_reuses = list_reuses;
         if (evaluated_valid) {
             unsigned long long h[3] = {0, 0, 0};
             PP_HIP(hipMemcpy(h, counters.p, sizeof(h), hipMemcpyDeviceToHost));
@@ -958,6 +1029,11 @@ int pp_plan_set_monopole(pp_plan* pl, double theta) {
     return PP_OK;
 }
 
+int pp_plan_set_skin(pp_plan* pl, double skin) {
+    if (!pl) return fail(PP_EINVAL, "plan is NULL");
+    return pl->b.set_skin(skin);
+}
+
 int pp_plan_set_monopole_relative(pp_plan* pl, double alpha, const float* acc_ref, int64_t n,
                                   void* stream) {
     if (!pl) return fail(PP_EINVAL, "plan is NULL");
@@ -999,6 +1075,7 @@ int pp_plan_set_tuning(pp_plan* pl, const pp_tuning* t) {
     PP_TRY(check_tuning(t));
     pl->b.tune = *t;
     pl->b.lists_valid = false;
+    pl->b.reuse_ready = false;
     return PP_OK;
 }
 
@@ -1049,6 +1126,8 @@ static int count_interactions(Batch& b, int64_t* counts, int64_t* total, hipStre
         return fail(PP_EINVAL, "the lists hold monopoles: count after pp_accel_f64 or with theta 0");
     if (b.lists_active)
         return fail(PP_EINVAL, "the lists cover the active targets only: count after pp_accel or pp_accel_f64");
+    if (b.lists_moved)
+        return fail(PP_EINVAL, "the lists were reused for moved particles: count after pp_accel_f64");
     PP_TRY(b.pcount.reserve(sizeof(int32_t) * kBlock * (b.w.cap_item + 1)));
     PP_TRY(launch_count(b.bd, b.w, b.pcount.as<int32_t>(), s));
     unsigned long long* tot = b.w.misc.as<unsigned long long>() + 4;

@@ -211,9 +211,17 @@ int pp_kdk_step(pp_kdk* k, double* pos, double* vel, const float* mass, double d
     return PP_OK;
 }
 
+int pp_kdk_set_skin(pp_kdk* k, double skin) {
+    if (!k) return fail(PP_EINVAL, "NULL argument");
+    return pp_plan_set_skin(k->plan, skin);
+}
+
 int pp_kdk_get_info(const pp_kdk* k, pp_kdk_info* out) {
     if (!k || !out) return fail(PP_EINVAL, "NULL argument");
     *out = k->info;
+    pp_stats st{};
+    PP_TRY(pp_plan_stats(k->plan, &st));
+    out->list_builds = st.list_builds;
     return PP_OK;
 }
 

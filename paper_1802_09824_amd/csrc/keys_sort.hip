@@ -190,6 +190,41 @@ __global__ void __launch_bounds__(256) gather_keys_kernel(const uint64_t* __rest
     out[k] = keys[perm[k]];
 }
 
+// Reuse of the lists: particle k of the stored key order (input particle
+// perm[k]) moves from its reference position by its minimum-image
+// displacement, so it stays at the periodic image the lists were built for;
+// its mass is gathered too.  A displacement of at least half_skin sets
+// sizes[kMoved] (the lists may then miss pairs and are rebuilt), a
+// non-finite position or mass the bad flag.
+__global__ void __launch_bounds__(256) regather_kernel(BatchDev bd, const double* __restrict__ pos,
+                                                       const float* __restrict__ mass,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ ref, int64_t N,
+                                                       int64_t n_in, double half_skin2,
+                                                       double* __restrict__ pos_s,
+                                                       float* __restrict__ mass_s,
+                                                       int64_t* __restrict__ sizes, int* __restrict__ bad) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int x = box_of(bd.poff, bd.nbox, k);
+    const double L = bd.box[x].L;
+    const int64_t i = perm[k];
+    double d2 = 0.0;
+    bool finite = true;
+    for (int a = 0; a < 3; ++a) {
+        const double xn = pos[a * n_in + i], xr = ref[a * N + k];
+        finite = finite && isfinite(xn);
+        double d = xn - xr;
+        d -= L * rint(d / L);
+        pos_s[a * N + k] = xr + d;
+        d2 += d * d;
+    }
+    const float m = mass[i];
+    mass_s[k] = m;
+    if (!finite || !isfinite(m)) *bad = 1;
+    else if (d2 >= half_skin2) sizes[kMoved] = 1;
+}
+
 // The key sort: one-sweep radix with 10-bit digits (7 passes over 63 key
 // bits instead of 8 with the library's 8-bit default for this target).
 using key_sort_config = rocprim::radix_sort_config<
@@ -286,6 +321,16 @@ int stage_sort(const BatchDev& bd, int64_t N, Work& w, hipStream_t s) {
                                      (size_t)N, 0, 16, s));
     hipLaunchKernelGGL(gather_keys_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s,
                        w.keys.as<uint64_t>(), w.perm.as<int32_t>(), N, w.keys_s.as<uint64_t>());
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
+int stage_regather(const BatchDev& bd, int64_t N, const double* pos, const float* mass,
+                   const double* ref, double half_skin, Work& w, hipStream_t s) {
+    if (N == 0) return PP_OK;
+    hipLaunchKernelGGL(regather_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, bd, pos, mass,
+                       w.perm.as<int32_t>(), ref, N, w.pos_n, half_skin * half_skin, w.pos_s.as<double>(),
+                       w.mass_s.as<float>(), w.sizes.as<int64_t>(), w.bad.as<int>());
     PP_HIP(hipGetLastError());
     return PP_OK;
 }

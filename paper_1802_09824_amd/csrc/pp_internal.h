@@ -121,7 +121,8 @@ struct BoxDev {
 int make_poly(const pp_box_params& p, PolyF32* out);
 // The FP32 kernel's length unit ell = 2 r_s sqrt(U_MAX / 2).
 double pair_length_unit(const pp_box_params& p);
-BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n);
+// skin > 0 widens the lists' cut to rcut + skin (the pair test keeps rcut)
+BoxDev make_boxdev(const pp_box_params& p, int64_t poff, int64_t n, double skin = 0.0);
 int validate_params(const pp_box_params* p, bool need_poly);
 
 // Box of particle (or chunk, leaf, ...) k given ascending start offsets:
@@ -179,6 +180,7 @@ enum SizeSlot : int {
     kNeedBlock = 11,
     kNeedRange = 12,
     kNeedItem = 13,
+    kMoved = 14,        // a call reusing the lists met a particle that moved half the skin or more
     kEntry0 = 16,       // kEntry0 + p: entries after expansion pass p (clamped)
     kNeedEntry0 = 40,   // kNeedEntry0 + p: the same, unclamped
     kSizeSlots = 64
@@ -310,13 +312,29 @@ struct MonoCfg {
 // active target get no work items (their outputs are left alone).
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
                 hipStream_t s, const MonoCfg& mono = MonoCfg(), const uint8_t* active = nullptr);
+// Work items of the current lists (after stage_lists, or on their own for a
+// call that reuses the lists): items per block for the given active flags,
+// their offsets, and the final counts.
+int stage_items(const BatchDev& bd, Work& w, hipStream_t s, const uint8_t* active);
 // Zero the count slots at the start of a pass.
 int reset_sizes(Work& w, hipStream_t s);
+// A pass that reuses the lists: clears the per-pass slots (candidates,
+// moved, skip, bad) and keeps the list counts.
+int reset_sizes_reuse(Work& w, hipStream_t s);
+// Positions and masses of a call that reuses the lists, in the stored key
+// order: every particle moves from its reference position (ref, [3][N], the
+// positions the lists were built at) by its minimum-image displacement, so
+// it keeps the periodic image the lists hold; a displacement of at least
+// half_skin sets the kMoved slot, a non-finite value the bad flag.
+int stage_regather(const BatchDev& bd, int64_t N, const double* pos, const float* mass,
+                   const double* ref, double half_skin, Work& w, hipStream_t s);
 // Reads the counts of the last pass back (synchronises the stream).  Sets
 // *regrow and grows the capacities when a buffer was too small (the pass must
-// then run again); PP_EINVAL when an input was not finite.  Otherwise fills
-// the host copies (nleaf, nblock, nentry, nrange, nitem, candidates, chunk).
-int lists_to_host(Work& w, hipStream_t s, bool* regrow);
+// then run again); sets *regrow and *moved when a pass that reused the lists
+// met a particle that moved too far (the lists must be rebuilt); PP_EINVAL
+// when an input was not finite.  Otherwise fills the host copies (nleaf,
+// nblock, nentry, nrange, nitem, candidates, chunk).
+int lists_to_host(Work& w, hipStream_t s, bool* regrow, bool* moved = nullptr);
 // Mass and mass-weighted position sums of every tree node (after stage_trees;
 // needs the FP32 masses in key order).
 int stage_node_moments(const BatchDev& bd, int64_t N, Work& w, hipStream_t s);

@@ -1016,7 +1016,17 @@ __global__ void finish_sizes_kernel(int64_t* __restrict__ sizes, const int64_t* 
     if (ni > cap_item) sizes[kOverflow] |= 8;
     if (nr > cap_range) sizes[kOverflow] |= 4;
     sizes[kBad] = bad ? *bad : 0;
-    sizes[kSkip] = (sizes[kOverflow] != 0 || sizes[kBad] != 0) ? 1 : 0;
+    sizes[kSkip] = (sizes[kOverflow] != 0 || sizes[kBad] != 0 || sizes[kMoved] != 0) ? 1 : 0;
+}
+
+// Per-pass slots of a pass that reuses the lists (the list counts stay).
+__global__ void zero_sizes_reuse_kernel(int64_t* __restrict__ sizes, int* __restrict__ bad) {
+    if (threadIdx.x != 0) return;
+    sizes[kCand] = 0;
+    sizes[kMoved] = 0;
+    sizes[kSkip] = 0;
+    sizes[kBad] = 0;
+    *bad = 0;
 }
 
 __global__ void zero_sizes_kernel(int64_t* __restrict__ sizes, int* __restrict__ bad) {
@@ -1055,6 +1065,13 @@ int reset_sizes(Work& w, hipStream_t s) {
     PP_TRY(w.sizes.reserve(sizeof(int64_t) * kSizeSlots));
     PP_TRY(w.bad.reserve(64));
     hipLaunchKernelGGL(zero_sizes_kernel, dim3(1), dim3(kSizeSlots), 0, s, w.sizes.as<int64_t>(),
+                       w.bad.as<int>());
+    PP_HIP(hipGetLastError());
+    return PP_OK;
+}
+
+int reset_sizes_reuse(Work& w, hipStream_t s) {
+    hipLaunchKernelGGL(zero_sizes_reuse_kernel, dim3(1), dim3(64), 0, s, w.sizes.as<int64_t>(),
                        w.bad.as<int>());
     PP_HIP(hipGetLastError());
     return PP_OK;
@@ -1380,23 +1397,29 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     constexpr int64_t kMaxItems = 1 << 21;
     hipLaunchKernelGGL(chunk_kernel, dim3(1), dim3(1), 0, s, (const int64_t*)w.soff_e.as<int64_t>(), sizes,
                        (int64_t)chunk_req, kMaxItems);
-    w.active = active;
-    hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
-                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), sizes, cb, active,
-                       w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>());
-    PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), cb, w.scan_ws, s, sizes));
     PP_TRY(w.rbeg.reserve(sizeof(int32_t) * (w.cap_range + 1)));
     PP_TRY(w.rpre.reserve(sizeof(int32_t) * (w.cap_range + 1)));
     PP_TRY(w.rcode.reserve(sizeof(uint8_t) * (w.cap_range + 1)));
-    PP_TRY(w.iblock.reserve(sizeof(int32_t) * (w.cap_item + 1)));
-    PP_TRY(w.is0.reserve(sizeof(int32_t) * (w.cap_item + 1)));
     hipLaunchKernelGGL(ranges_fill_kernel, dim3(blocks_for(F, 128)), dim3(128), 0, s, bd, tvs, nodes, ent,
                        F, bbox, bboxid, lbegin, lcount, w.lmask_e.as<uint64_t>(),
                        (const int64_t*)w.roff_e.as<int64_t>(), (const int64_t*)w.soff_e.as<int64_t>(),
                        (const int64_t*)w.eoff.as<int64_t>(), w.rbeg.as<int32_t>(), w.rpre.as<int32_t>(),
                        w.rcode.as<uint8_t>(), mono, (const int64_t*)sizes, w.cap_range);
     PP_HIP(hipGetLastError());
+    return stage_items(bd, w, s, active);
+}
+
+int stage_items(const BatchDev& bd, Work& w, hipStream_t s, const uint8_t* active) {
+    int64_t* sizes = w.sizes.as<int64_t>();
+    const int64_t cb = w.cap_block;
+    w.active = active;
+    hipLaunchKernelGGL(item_count_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
+                       w.slen.as<int32_t>(), w.bcount.as<int32_t>(), sizes, cb, active,
+                       w.perm.as<int32_t>(), w.bstart.as<int32_t>(), w.icount.as<int32_t>());
+    PP_HIP(hipGetLastError());
+    PP_TRY(launch_scan_i32_to_i64(w.icount.as<int32_t>(), w.ioff.as<int64_t>(), cb, w.scan_ws, s, sizes));
+    PP_TRY(w.iblock.reserve(sizeof(int32_t) * (w.cap_item + 1)));
+    PP_TRY(w.is0.reserve(sizeof(int32_t) * (w.cap_item + 1)));
     hipLaunchKernelGGL(item_fill_kernel, dim3(blocks_for(cb, 256)), dim3(256), 0, s,
                        w.icount.as<int32_t>(), w.ioff.as<int64_t>(), (const int64_t*)sizes, w.cap_item,
                        w.iblock.as<int32_t>(), w.is0.as<int32_t>());
@@ -1406,13 +1429,19 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     return PP_OK;
 }
 
-int lists_to_host(Work& w, hipStream_t s, bool* regrow) {
+int lists_to_host(Work& w, hipStream_t s, bool* regrow, bool* moved) {
     *regrow = false;
+    if (moved) *moved = false;
     PP_TRY(w.sizes_h.reserve(sizeof(int64_t) * kSizeSlots));
     int64_t* h = w.sizes_h.as<int64_t>();
     PP_HIP(hipMemcpyAsync(h, w.sizes.p, sizeof(int64_t) * kSizeSlots, hipMemcpyDeviceToHost, s));
     PP_HIP(hipStreamSynchronize(s));
     if (h[kBad]) return fail(PP_EINVAL, "non-finite position or mass");
+    if (h[kMoved]) {                    // reused lists no longer cover every pair: rebuild
+        if (moved) *moved = true;
+        *regrow = true;
+        return PP_OK;
+    }
     if (h[kOverflow] & 64) return fail(PP_EDEVICE, "the list builder's single-pass scan did not complete");
     if (h[kOverflow] & 16) return fail(PP_ERANGE, "a target block lists more than 2^31 sources");
     if (h[kOverflow]) {

@@ -27,7 +27,10 @@ def dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def test_kdk_matches_oracle_integration(pp):
+@pytest.mark.parametrize("skin", [0.0, 0.4])
+def test_kdk_matches_oracle_integration(pp, skin):
+    """With a skin the substeps reuse the short-range lists; the trajectory
+    must meet the same bars (the pair test is exact either way)."""
     import oracle
     from oracle import kdk as okdk, pm as opm
     rng = np.random.default_rng(11)
@@ -44,6 +47,7 @@ def test_kdk_matches_oracle_integration(pp):
         return oracle.accel(x, m64, p)["acc"] + opm.pm_accel(x, m64, p, nm)
 
     K = pp.KDK(p, n, n_mesh=nm, eta=eta, max_level=kmax)
+    K.set_skin(skin)
     P, V, M = dev(pos0, torch.float64), dev(vel0, torch.float64), dev(mass, torch.float32)
     K.init(P, M)
     po, vo = pos0.copy(), vel0.copy()
@@ -68,6 +72,11 @@ def test_kdk_matches_oracle_integration(pp):
         targets += int((2 ** lev).sum())
         assert info["short_range_targets"] == targets < n * evals
     assert len(set(lev.tolist())) >= 2              # the test exercises several levels
+    info = K.info()
+    if skin > 0:
+        assert 1 <= info["list_builds"] < info["force_evaluations"] / 2, info
+    else:
+        assert info["list_builds"] == info["force_evaluations"]
     pg, vg = P.cpu().numpy(), V.cpu().numpy()
     dp = pg - po
     dp -= L * np.round(dp / L)
@@ -112,6 +121,9 @@ def test_kdk_argument_checks(pp):
     x = torch.rand((3, 10), dtype=torch.float64, device="cuda") * 10
     with pytest.raises(pp.PPError):            # init first
         K.step(x, torch.zeros_like(x), torch.ones(10, dtype=torch.float32, device="cuda"), 0.1)
+    for bad in (-0.1, float("nan"), 5.0 - 2.25):   # negative, non-finite, rcut + skin = L/2
+        with pytest.raises(pp.PPError):
+            K.set_skin(bad)
 
 
 def test_kdk_short_range_only_matches_oracle(pp):
