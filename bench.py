@@ -292,9 +292,10 @@ def bench_kdk(box, pos, mass, acc_exact, n_mesh=128, eta=0.025, max_level=6, ste
             "level_count": i1["level_count"][:max_level + 1]}
 
 
-def bench_small_box(steps=20):
-    """The 32,768-particle uniform box (L = 100): a launch-latency case, one
-    whole pp_accel step per call."""
+def bench_small_box(steps=20, tune=True):
+    """The 32,768-particle uniform box (L = 100), one whole pp_accel step
+    per call: few work items, so the tiles are autotuned for it like the
+    headline box's (default tiles reported beside)."""
     import torch
     import workloads
     import paper_1802_09824_amd as pp
@@ -304,17 +305,23 @@ def bench_small_box(steps=20):
     plan = pp.Plan(b.params, b.n)
     acc = plan.accel(pos, mass)
     inter = plan.count_interactions()
-    for _ in range(3):
-        plan.accel(pos, mass, out=acc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.accel(pos, mass, out=acc)
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
+
+    def timed():
+        for _ in range(3):
+            plan.accel(pos, mass, out=acc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.accel(pos, mass, out=acc)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    sec_default = timed()
+    tuning = plan.autotune(pos, mass) if tune else plan.get_tuning()
+    sec = timed()
     del plan
     return {"workload": b.name, "n": b.n, "interactions_per_step": inter, "ms_per_step": 1e3 * sec,
-            "interactions_per_s": inter / sec}
+            "interactions_per_s": inter / sec, "tuning": tuning, "ms_per_step_default_tiles": 1e3 * sec_default}
 
 
 def bench_pm(box, pos, mass, n_mesh, steps, with_error=True):

@@ -170,7 +170,8 @@ class Leaves:
         self._h = C.c_void_p(handle)
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # (at interpreter exit the module's _lib may already be gone)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.pp_leaves_free(self._h)
             self._h = C.c_void_p(None)
 
@@ -206,7 +207,8 @@ class Pairs:
         self._h = C.c_void_p(handle)
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # (at interpreter exit the module's _lib may already be gone)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.pp_pairs_free(self._h)
             self._h = C.c_void_p(None)
 
@@ -241,7 +243,8 @@ class Plan:
         self._h = h
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # (at interpreter exit the module's _lib may already be gone)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.pp_plan_destroy(self._h)
             self._h = C.c_void_p(None)
 
@@ -396,7 +399,8 @@ class BatchPlan:
         self._h = h
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # (at interpreter exit the module's _lib may already be gone)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.pp_batch_plan_destroy(self._h)
             self._h = C.c_void_p(None)
 

@@ -588,13 +588,20 @@ struct Batch {
         // 1) the j tile: source-list positions per wave, and K waves per
         //    target block (a block's i tile of 64 targets swept by K waves),
         //    persistent at 20 waves per CU
-        const int chunks[] = {1024, 2048, 4096};
         const int ks[] = {1, 2, 4};
-        for (int c : chunks)
+        for (int c : {1024, 2048, 4096})
             for (int k : ks) {
                 if (k > 1 && !multi) continue;
                 PP_TRY(trial(pp_tuning{c * k, 1, 20, batch ? 1 : 0, variant, k}));
             }
+        // lists too short to give every SIMD several items at 1024 positions
+        // per wave (small boxes): shorter j tiles too
+        if (w.total_src < (int64_t)16384 * 1024)
+            for (int c : {256, 512})
+                for (int k : ks) {
+                    if (k > 1 && !multi) continue;
+                    PP_TRY(trial(pp_tuning{c * k, 1, 20, batch ? 1 : 0, variant, k}));
+                }
         // 2) the launch shape at that tiling: resident waves per CU, or one
         //    workgroup per item
         const pp_tuning tiled = best;

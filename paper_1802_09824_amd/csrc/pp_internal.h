@@ -242,6 +242,7 @@ struct Work {
     // blocks, lists, items (host copies, valid after lists_to_host)
     int64_t nchunk = 0, nblock = 0, nentry = 0, nrange = 0, nitem = 0;
     int64_t candidates = 0;
+    int64_t total_src = 0;     // listed sources summed over the blocks
     int chunk = 0;           // effective chunk of the current items (>= the requested one)
     std::vector<int64_t> choff_h;         // chunk offsets of the boxes (host)
     DevBuf choff, ccount, coff;
@@ -269,10 +270,19 @@ int sort_workspace(int64_t n, int nbox, int bits, size_t* bytes);
 int scan_workspace(int64_t n, size_t* bytes);
 // reserves the workspace for n counts; fresh memory is cleared on stream s
 int grow_scan(DevBuf& buf, int64_t n, hipStream_t s);
+// Count slots a scan fills with its total (see launch_scan_i32_to_i64).
+struct ScanNote {
+    int slot, need_slot;
+    int64_t cap;
+    unsigned long long bit;
+    int slot2;                  // >= 0: gets the clamped total as well
+};
 // exclusive scan of int32 counts into int64 offsets; off has n + 1 entries
-// (off[n] = total); sizes, when given, gets overflow bit 6 if the scan gave up
+// (off[n] = total); sizes, when given, gets overflow bit 6 if the scan gave
+// up; with a note (needs sizes) also sizes[need_slot] = total,
+// sizes[slot] = min(total, cap) and `bit` in the overflow slot when over
 int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s,
-                           int64_t* sizes = nullptr);
+                           int64_t* sizes = nullptr, const ScanNote* note = nullptr);
 // the same for two count arrays of equal length in one pass
 int launch_scan2_i32_to_i64(const int32_t* a, const int32_t* b, int64_t* oa, int64_t* ob, int64_t n,
                             DevBuf& ws, hipStream_t s, int64_t* sizes = nullptr);

@@ -1,95 +1,44 @@
-// Single-pass exclusive scans of int32 counts into int64 offsets (decoupled
-// look-back), used by every stage that turns per-item counts into output
-// positions.
-//
-// A workgroup sums a tile of kScanTile counts.  It takes its tile number
-// from a ticket counter, so every tile it may wait for has already started
-// and publishes without waiting itself.  Per scanned array it publishes one
-// 64-bit word: (aggregate << 2) | 1, later (inclusive prefix << 2) | 2;
-// 0 means not yet published.  Its exclusive prefix is the sum of the words
-// of the tiles before it, walked back to the first inclusive one.  A word
-// is read and written whole by agent-scope atomics, so a value and its flag
-// are never seen apart.
-//
-// Workspace (uint64): two regions, each a ticket and the words, used by
-// consecutive scans in turn.  A region is zero whenever a scan starts in it:
-// both are cleared when allocated, and every scan clears the other region
-// (the one its predecessor used, and its successor will use).  A wait that
-// does not end within kSpins polls gives up and sets overflow bit 6 of the
-// count slots (when given), so that the call fails instead of hanging.
-#include "pp_internal.h"
+// Single-pass exclusive scans of int32 counts into int64 offsets, used by
+// every stage that turns per-item counts into output positions: tiles of
+// kScanTile counts with decoupled look-back between them (lookback.h).
+#include "lookback.h"
 
 namespace pp {
 namespace {
 
 constexpr int kScanWG = 256;
-constexpr int kScanIPT = 8;
-constexpr int64_t kScanTile = (int64_t)kScanWG * kScanIPT;
-constexpr int kSpins = 1 << 22;
-
+template <int NV>
+struct ScanTile {
+    static constexpr int kIPT = 8;
+    static constexpr int64_t kSize = (int64_t)kScanWG * kIPT;
+};
+constexpr int64_t kScanMinTile = ScanTile<2>::kSize;
 struct ScanIO {
     const int32_t* in[2];
     int64_t* out[2];
 };
-
-__device__ __forceinline__ void publish(unsigned long long* w, int64_t v, unsigned st) {
-    __hip_atomic_store(w, ((unsigned long long)v << 2) | st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive prefix of `tile` for array c of NV, walked back by a whole wave
-// after the tile's aggregate was published: each lane reads one of the 64
-// nearest earlier tiles (lane 0 the nearest), waits until it is published,
-// and the wave adds the words up to the nearest inclusive one; with none
-// among them it adds all 64 and moves 64 tiles further back.  Tiles before
-// the first count as an inclusive zero.
-template <int NV>
-__device__ int64_t walk_back(const unsigned long long* words, int64_t tile, int c, int64_t* sizes,
-                             int lane) {
-    int64_t excl = 0;
-    for (int64_t j = tile - 1;; j -= 64) {
-        const int64_t k = j - lane;
-        unsigned long long w = 2ull;
-        if (k >= 0) {
-            for (int spin = 0;; ++spin) {
-                w = __hip_atomic_load(words + k * NV + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (w & 3ull) break;
-                if (spin > kSpins) {
-                    if (sizes) atomicOr(reinterpret_cast<unsigned long long*>(sizes + kOverflow), 64ull);
-                    w = 2ull;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        const unsigned long long incl = __ballot((w & 3ull) == 2ull);
-        const int stop = incl ? __builtin_ctzll(incl) : 64;
-        int64_t v = lane <= stop ? (int64_t)(w >> 2) : 0;
-        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-        excl += v;
-        if (incl) return excl;
-    }
-}
 
 // out[c][i] = sum of in[c][0 .. i) for i in [0, n]; ntile = tiles over n + 1.
 // `cur` is this scan's region (ticket, then words), `other` the region to
 // clear (nclear words).  The tile's counts come in and its offsets go out
 // through LDS, so that the global loads and stores of a wave are contiguous
 // while every thread scans kScanIPT consecutive counts.
+// With note.slot >= 0 the last tile also records the total of array 0 in
+// the count slots: sizes[need_slot] = total, sizes[slot] (and slot2) =
+// min(total, cap), and the overflow bit when total > cap.
 template <int NV>
-__global__ __launch_bounds__(kScanWG) void scan_counts_kernel(ScanIO io, int64_t n,
-                                                              unsigned long long* cur,
-                                                              unsigned long long* other, int64_t nclear,
-                                                              int64_t* sizes) {
+__global__ __launch_bounds__(kScanWG) void scan_counts_kernel(ScanIO io, int64_t n, LbArgs lb,
+                                                              int64_t* sizes, int64_t ntile, ScanNote note) {
+    constexpr int kScanIPT = ScanTile<NV>::kIPT;
+    constexpr int64_t kScanTile = ScanTile<NV>::kSize;
     __shared__ int32_t s_in[NV][kScanTile];
     __shared__ int64_t s_out[NV][kScanTile];
     __shared__ unsigned s_tile;
     __shared__ int64_t s_wave[NV][kScanWG / 64];
     __shared__ int64_t s_pre[NV];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    unsigned long long* words = cur + 1;
-    for (int64_t i = (int64_t)blockIdx.x * kScanWG + t; i < nclear; i += (int64_t)gridDim.x * kScanWG)
-        other[i] = 0ull;
-    if (t == 0) s_tile = (unsigned)atomicAdd(cur, 1ull);
+    lb_clear_other(lb);
+    if (t == 0) s_tile = (unsigned)atomicAdd(lb.cur, 1ull);
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t t0 = tile * kScanTile;
@@ -140,16 +89,19 @@ __global__ __launch_bounds__(kScanWG) void scan_counts_kernel(ScanIO io, int64_t
         const int c = wave;
         int64_t agg = 0;
         for (int k = 0; k < kScanWG / 64; ++k) agg += s_wave[c][k];
-        unsigned long long* w = words + tile * NV + c;
-        int64_t ex = 0;
-        if (tile == 0) {
-            if (lane == 0) publish(w, agg, 2u);
-        } else {
-            if (lane == 0) publish(w, agg, 1u);
-            ex = walk_back<NV>(words, tile, c, sizes, lane);
-            if (lane == 0) publish(w, ex + agg, 2u);
+        const int64_t ex = lb_tile_prefix<NV>(lb, tile, c, agg, sizes, lane);
+        if (lane == 0) {
+            s_pre[c] = ex;
+            if (c == 0 && note.slot >= 0 && tile == ntile - 1) {
+                const int64_t total = ex + agg;
+                const int64_t kept = total < note.cap ? total : note.cap;
+                sizes[note.need_slot] = total;
+                sizes[note.slot] = kept;
+                if (note.slot2 >= 0) sizes[note.slot2] = kept;
+                if (total > note.cap)
+                    atomicOr(reinterpret_cast<unsigned long long*>(sizes + kOverflow), note.bit);
+            }
         }
-        if (lane == 0) s_pre[c] = ex;
     }
     __syncthreads();
 #pragma unroll
@@ -183,39 +135,62 @@ __global__ void set_zero2_kernel(int64_t* a, int64_t* b) {
     if (b) *b = 0;
 }
 
-int64_t tiles_for(int64_t n) { return (n + 1 + kScanTile - 1) / kScanTile; }
+template <int NV>
+int64_t tiles_for(int64_t n) { return (n + 1 + ScanTile<NV>::kSize - 1) / ScanTile<NV>::kSize; }
+
+// look-back words for n counts of each of up to two arrays
+int64_t words_for(int64_t n) { return 2 * ((n + 1 + kScanMinTile - 1) / kScanMinTile) + 2; }
+
+__global__ void note_zero_kernel(int64_t* __restrict__ sizes, ScanNote note) {
+    sizes[note.need_slot] = 0;
+    sizes[note.slot] = 0;
+    if (note.slot2 >= 0) sizes[note.slot2] = 0;
+}
 
 template <int NV>
-int launch(const ScanIO& io, int64_t n, DevBuf& ws, hipStream_t s, int64_t* sizes) {
+int launch(const ScanIO& io, int64_t n, DevBuf& ws, hipStream_t s, int64_t* sizes, const ScanNote* note) {
+    if (note && !sizes) return fail(PP_EINVAL, "a scan note needs the count slots");
     if (n == 0) {
         hipLaunchKernelGGL(set_zero2_kernel, dim3(1), dim3(1), 0, s, io.out[0], NV > 1 ? io.out[1] : nullptr);
+        if (note) hipLaunchKernelGGL(note_zero_kernel, dim3(1), dim3(1), 0, s, sizes, *note);
         PP_HIP(hipGetLastError());
         return PP_OK;
     }
-    PP_TRY(grow_scan(ws, NV * n, s));
-    const int64_t nt = tiles_for(n);
-    const int64_t region = (int64_t)(ws.bytes / sizeof(unsigned long long)) / 2;
-    unsigned long long* base = ws.as<unsigned long long>();
-    if (1 + nt * NV > region) return fail(PP_EDEVICE, "scan workspace smaller than its tiles");
-    const uint32_t r = ws.tag & 1u;             // the region this scan uses
-    hipLaunchKernelGGL(scan_counts_kernel<NV>, dim3((unsigned)nt), dim3(kScanWG), 0, s, io, n,
-                       base + r * region, base + (1 - r) * region, region, sizes);
+    const int64_t nt = tiles_for<NV>(n);
+    PP_TRY(grow_lookback(ws, nt * NV, s));
+    LbArgs lb;
+    PP_TRY(lookback_args(ws, nt * NV, &lb));
+    const ScanNote none{-1, -1, 0, 0ull, -1};
+    hipLaunchKernelGGL(scan_counts_kernel<NV>, dim3((unsigned)nt), dim3(kScanWG), 0, s, io, n, lb, sizes, nt,
+                       note ? *note : none);
     PP_HIP(hipGetLastError());
-    ws.tag ^= 1u;
     return PP_OK;
 }
 
 }  // namespace
 
 int scan_workspace(int64_t n, size_t* bytes) {
-    // two regions of a ticket and one word per tile (two arrays take n = 2 x count)
-    *bytes = 2 * sizeof(unsigned long long) * (size_t)(1 + tiles_for(n) + 2);
+    // two regions of a ticket and the words
+    *bytes = 2 * sizeof(unsigned long long) * (size_t)(1 + words_for(n) + 2);
     return PP_OK;
 }
 
-int grow_scan(DevBuf& buf, int64_t n, hipStream_t s) {
-    size_t need = 0;
-    PP_TRY(scan_workspace(n, &need));
+int grow_scan(DevBuf& buf, int64_t n, hipStream_t s) { return grow_lookback(buf, words_for(n), s); }
+
+int lookback_args(DevBuf& ws, int64_t words, LbArgs* out) {
+    const int64_t region = (int64_t)(ws.bytes / sizeof(unsigned long long)) / 2;
+    if (1 + words > region) return fail(PP_EDEVICE, "look-back workspace smaller than its tiles");
+    unsigned long long* base = ws.as<unsigned long long>();
+    const uint32_t r = ws.tag & 1u;             // the region this kernel uses
+    out->cur = base + r * region;
+    out->other = base + (1 - r) * region;
+    out->nclear = region;
+    ws.tag ^= 1u;
+    return PP_OK;
+}
+
+int grow_lookback(DevBuf& buf, int64_t words, hipStream_t s) {
+    const size_t need = 2 * sizeof(unsigned long long) * (size_t)(1 + words + 2);
     const uint64_t gen = alloc_generation();
     PP_TRY(buf.reserve(need));
     if (alloc_generation() != gen) {            // fresh memory: clear all of it
@@ -229,15 +204,15 @@ int grow_scan(DevBuf& buf, int64_t n, hipStream_t s) {
 }
 
 int launch_scan_i32_to_i64(const int32_t* in, int64_t* off, int64_t n, DevBuf& ws, hipStream_t s,
-                           int64_t* sizes) {
+                           int64_t* sizes, const ScanNote* note) {
     ScanIO io{{in, nullptr}, {off, nullptr}};
-    return launch<1>(io, n, ws, s, sizes);
+    return launch<1>(io, n, ws, s, sizes, note);
 }
 
 int launch_scan2_i32_to_i64(const int32_t* a, const int32_t* b, int64_t* oa, int64_t* ob, int64_t n,
                             DevBuf& ws, hipStream_t s, int64_t* sizes) {
     ScanIO io{{a, b}, {oa, ob}};
-    return launch<2>(io, n, ws, s, sizes);
+    return launch<2>(io, n, ws, s, sizes, nullptr);
 }
 
 }  // namespace pp

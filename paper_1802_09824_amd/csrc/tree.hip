@@ -170,27 +170,32 @@ __global__ void __launch_bounds__(256) tree_views_kernel(const int64_t* __restri
                                                          TreeView* __restrict__ tv,
                                                          int64_t* __restrict__ lp,
                                                          int64_t* __restrict__ total) {
-    __shared__ int64_t part[256];
-    const int t = threadIdx.x;
+    __shared__ int64_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int per = (nbox + 255) / 256;
     const int x0 = t * per < nbox ? t * per : nbox;
     const int x1 = x0 + per < nbox ? x0 + per : nbox;
     int64_t base = 0;                     // first node of level h (same in every thread)
-    for (int h = 0; h < kTreeMaxLevels; ++h) {
+    int h = 0;
+    for (; h < kTreeMaxLevels; ++h) {
         int64_t sum = 0;
         for (int x = x0; x < x1; ++x) sum += level_count(loff[x + 1] - loff[x], h);
-        // inclusive scan of the 256 thread sums (Hillis-Steele in LDS)
-        part[t] = sum;
-        __syncthreads();
-        for (int d = 1; d < 256; d <<= 1) {
-            const int64_t v = t >= d ? part[t - d] : 0;
-            __syncthreads();
-            part[t] += v;
-            __syncthreads();
+        // inclusive scan of the 256 thread sums: inside each wave, then the
+        // four wave totals
+        int64_t inc = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t u = __shfl_up(inc, d);
+            if (lane >= d) inc += u;
         }
-        const int64_t level_total = part[255];
-        int64_t acc = part[t] - sum;      // nodes of this level before box x0
+        if (lane == 63) wsum[wave] = inc;
         __syncthreads();
+        int64_t before = 0, level_total = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < wave) before += wsum[k];
+            level_total += wsum[k];
+        }
+        __syncthreads();                  // wsum is rewritten at the next level
+        int64_t acc = before + inc - sum;  // nodes of this level before box x0
         for (int x = x0; x < x1; ++x) {
             const int64_t c0 = loff[x + 1] - loff[x];
             const int64_t c = level_count(c0, h);
@@ -209,6 +214,16 @@ __global__ void __launch_bounds__(256) tree_views_kernel(const int64_t* __restri
         }
         if (t == 0) lp[(int64_t)h * (nbox + 1) + nbox] = level_total;
         base += level_total;
+        if (level_total == 0) break;      // no box has nodes here or above
+    }
+    // the levels above the last populated one: empty
+    for (++h; h < kTreeMaxLevels; ++h) {
+        for (int x = x0; x < x1; ++x) {
+            lp[(int64_t)h * (nbox + 1) + x] = 0;
+            tv[x].cnt[h] = 0;
+            tv[x].off[h] = 0;
+        }
+        if (t == 0) lp[(int64_t)h * (nbox + 1) + nbox] = 0;
     }
     if (t == 0) total[0] = base;
 }
@@ -992,15 +1007,6 @@ __global__ void item_fill_kernel(const int32_t* __restrict__ icount,
     }
 }
 
-// count slot <- min(total, cap); need slot <- total; overflow bit when over
-__global__ void note_count_kernel(int64_t* __restrict__ sizes, const int64_t* __restrict__ total,
-                                  int slot, int need_slot, int64_t cap, unsigned long long bit) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const int64_t t = *total;
-    sizes[need_slot] = t;
-    sizes[slot] = t < cap ? t : cap;
-    if (t > cap) sizes[kOverflow] |= (int64_t)bit;
-}
 
 // Item and range totals, and the flag that makes the PP kernels return.
 __global__ void finish_sizes_kernel(int64_t* __restrict__ sizes, const int64_t* __restrict__ ioff,
@@ -1286,9 +1292,11 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                            (IBox*)nullptr, (int32_t*)nullptr, cb);
         PP_HIP(hipGetLastError());
     }
-    PP_TRY(launch_scan_i32_to_i64(w.ccount.as<int32_t>(), w.coff.as<int64_t>(), nc, w.scan_ws, s, sizes));
-    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.coff.as<int64_t>() + nc,
-                       (int)kNBlock, (int)kNeedBlock, cb, 1ull);
+    {
+        const ScanNote note{(int)kNBlock, (int)kNeedBlock, cb, 1ull, -1};
+        PP_TRY(launch_scan_i32_to_i64(w.ccount.as<int32_t>(), w.coff.as<int64_t>(), nc, w.scan_ws, s, sizes,
+                                      &note));
+    }
     if (nc > 0)
         hipLaunchKernelGGL(block_split_kernel<true>, dim3((unsigned)nc), dim3(kBlock), 0, s, bd,
                            pos_s, N, w.choff.as<int64_t>(), nc, (int32_t*)nullptr,
@@ -1327,9 +1335,11 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                        nodes, bbox, bboxid, (const int64_t*)sizes, cb, w.fcnt.as<int32_t>(),
                        (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
     PP_HIP(hipGetLastError());
-    PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cb, w.scan_ws, s, sizes));
-    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cb,
-                       (int)kEntry0, (int)kNeedEntry0, w.cap_ent[0], 2ull);
+    {
+        const ScanNote note{(int)kEntry0, (int)kNeedEntry0, w.cap_ent[0], 2ull, npass == 1 ? (int)kNEntry : -1};
+        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cb, w.scan_ws, s, sizes,
+                                      &note));
+    }
     hipLaunchKernelGGL(bfs_root_kernel<true>, dim3(blocks_for(cb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, (const int64_t*)sizes, cb, (int32_t*)nullptr,
                        w.foff.as<int64_t>(), w.fent_a.as<FEntry>(), w.cap_ent[0], mono);
@@ -1344,9 +1354,10 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
                            (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, w.fcnt.as<int32_t>(),
                            (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
         PP_HIP(hipGetLastError());
-        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cin, w.scan_ws, s, sizes));
-        hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes, w.foff.as<int64_t>() + cin,
-                           (int)(kEntry0 + p), (int)(kNeedEntry0 + p), cout, 2ull);
+        const ScanNote note{(int)(kEntry0 + p), (int)(kNeedEntry0 + p), cout, 2ull,
+                            p == npass - 1 ? (int)kNEntry : -1};
+        PP_TRY(launch_scan_i32_to_i64(w.fcnt.as<int32_t>(), w.foff.as<int64_t>(), cin, w.scan_ws, s, sizes,
+                                      &note));
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd, tvs,
                            nodes, bbox, bboxid, cur->as<FEntry>(),
                            (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, (int32_t*)nullptr,
@@ -1357,9 +1368,6 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         nxt = t;
     }
     const int64_t F = w.cap_ent[npass - 1];    // the final entry buffer's capacity
-    hipLaunchKernelGGL(note_count_kernel, dim3(1), dim3(1), 0, s, sizes,
-                       (const int64_t*)(sizes + kEntry0 + npass - 1), (int)kNEntry,
-                       (int)(kNeedEntry0 + kMaxPasses - 1), F, 0ull);
     const FEntry* ent = cur->as<FEntry>();
     w.ent_final = ent;
     PP_TRY(w.lmask_e.reserve(sizeof(uint64_t) * (F + 1)));
@@ -1470,6 +1478,7 @@ int lists_to_host(Work& w, hipStream_t s, bool* regrow, bool* moved) {
     w.nrange = h[kNRange];
     w.nitem = h[kNItem];
     w.candidates = h[kCand];
+    w.total_src = h[kTotalSrc];
     w.chunk = (int)h[kChunk];
     return PP_OK;
 }
