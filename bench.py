@@ -648,7 +648,7 @@ def main():
     if not args.no_extras:
         out["monopoles"] = bench_monopoles(plan, box, pos, mass)
         kdk = bench_kdk(box, pos, mass, acc)
-        reuse = bench_kdk(box, pos, mass, acc, skin=0.05 * box.params.rcut)
+        reuse = bench_kdk(box, pos, mass, acc, skin=0.2 * box.params.rcut)
         kdk["list_reuse"] = {k: reuse[k] for k in ("skin", "ms_per_top_step", "list_builds_per_top_step",
                                                    "force_evaluations_per_top_step")}
         kdk["list_reuse"]["speedup"] = kdk["ms_per_top_step"] / reuse["ms_per_top_step"]

@@ -344,8 +344,8 @@ struct Batch {
     // *again set, a buffer was too small or a reusing pass met a particle
     // that moved too far (the PP kernels did nothing), and the pass must run
     // again, with the grown capacities or rebuilt lists.
-    int finish(hipStream_t s, bool* again) {
-        PP_TRY(lists_to_host(w, s, again));
+    int finish(hipStream_t s, bool* again, bool* moved = nullptr) {
+        PP_TRY(lists_to_host(w, s, again, moved));
         if (*again) {
             evaluated_valid = false;
             return PP_OK;
@@ -368,17 +368,23 @@ struct Batch {
                   const uint8_t* active = nullptr) {
         for (int attempt = 0; attempt < 32; ++attempt) {
             const bool reuse = can_reuse();
+            const int64_t cap_item0 = w.cap_item;
             if (reuse) PP_TRY(prepare_reuse(pos, mass, s, active));
             else PP_TRY(prepare(pos, mass, nullptr, s, active));
             PP_TRY(run_f32(acc, s));
-            bool again = false;
-            PP_TRY(finish(s, &again));
+            bool again = false, moved = false;
+            PP_TRY(finish(s, &again, &moved));
             if (again) {
-                reuse_ready = false;            // rebuild (and regrow) next
+                // a particle moved too far: rebuild; a reusing pass that only
+                // ran out of work items reuses again with more
+                if (moved || !reuse) reuse_ready = false;
                 continue;
             }
             if (reuse) {
                 ++list_reuses;
+                // the item count follows the active flags of each call: keep
+                // the capacity a fuller call needed
+                if (w.cap_item < cap_item0) w.cap_item = cap_item0;
             } else {
                 ++list_builds;
                 if (skin > 0.0 && !lists_mono) {

@@ -1025,9 +1025,11 @@ __global__ void finish_sizes_kernel(int64_t* __restrict__ sizes, const int64_t* 
     sizes[kSkip] = (sizes[kOverflow] != 0 || sizes[kBad] != 0 || sizes[kMoved] != 0) ? 1 : 0;
 }
 
-// Per-pass slots of a pass that reuses the lists (the list counts stay).
+// Per-pass slots of a pass that reuses the lists (the list counts stay; the
+// overflow bits of the last pass go, since the lists' own buffers fitted).
 __global__ void zero_sizes_reuse_kernel(int64_t* __restrict__ sizes, int* __restrict__ bad) {
     if (threadIdx.x != 0) return;
+    sizes[kOverflow] = 0;
     sizes[kCand] = 0;
     sizes[kMoved] = 0;
     sizes[kSkip] = 0;

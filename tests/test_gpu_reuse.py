@@ -197,3 +197,33 @@ def test_skin_argument_checks(pp):
         plan.set_skin(L / 2 - P_.rcut)
     assert e.value.code == pp.PP_ERANGE
     plan.set_skin(0.0)
+
+
+def test_reuse_survives_changing_active_sets(pp, box, oracle_mod):
+    """A time integrator's substeps alternate small and large active sets:
+    a call that needs more work items than the last one grows them and
+    still reuses the lists (64-position chunks make the item counts large
+    enough to overflow)."""
+    pos, mass = box
+    rng = np.random.default_rng(7)
+    n = pos.shape[1]
+    plan = pp.Plan(P_, n)
+    plan.set_skin(SKIN)
+    plan.set_tuning(chunk=64, waves_per_block=1)
+    M = dev(mass, torch.float32)
+    out = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    x = pos
+    items = []
+    for k, frac in enumerate((0.02, 1.0, 0.1, 1.0, 0.02, 0.5)):
+        if k:
+            x = moved(pos, rng, 0.45 * SKIN)
+        act = x[0] < frac * L                 # a slab: few target blocks when thin
+        plan.accel_active(dev(x, torch.float64), M, dev(act.astype(np.uint8), torch.uint8), out=out)
+        st = plan.stats()
+        assert (st["list_builds"], st["list_reuses"]) == (1, k), (k, st)
+        items.append(st["nitem"])
+        a = out.cpu().numpy()
+        ref = oracle_mod.accel(x, mass.astype(np.float64), P_)["acc"]
+        e = np.linalg.norm(a[:, act] - ref[:, act], axis=0) / np.linalg.norm(ref[:, act], axis=0)
+        assert np.median(e) <= 1e-6 and np.percentile(e, 99.9) <= 1e-4, (k, np.median(e))
+    assert items[1] > items[0] + items[0] // 4 + 1024     # the full call outgrew the first one's items
