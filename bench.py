@@ -44,11 +44,13 @@ TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "51d5883524584880335d2139c8d056ca875a8f95",
-    "fetch_bytes": 367515959,     # FETCH_SIZE 179456.9 KiB x 1.9999
-    "write_bytes": 116576000,     # WRITE_SIZE 113843.8 KiB x 1.0000
-    "fetch_scale": 1.9999,           # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
-    "write_scale": 1.0000,           # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
+    "sha1": "361885f4548456d40ac93fffbc9e0145db1ae318",
+    "fetch_bytes": 375546195,     # FETCH_SIZE 183376.2 KiB x 1.99996
+    "write_bytes": 196076960,     # WRITE_SIZE 191481.4 KiB x 1.00000
+    "fetch_scale": 1.99996,          # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
+    "write_scale": 1.00000,          # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
+    # the launch shape the counters were taken at (chunk, waves per block, waves per CU)
+    "tuning": (8192, 4, 20),
 }
 
 
@@ -61,11 +63,13 @@ def sources_sha1(files):
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(tuning=None):
     """HBM bytes per launch of the PP kernel, or None if not measured for
-    the current kernel sources."""
+    the current kernel sources and (when given) this launch shape."""
     t = TRAFFIC
     if t["sha1"] is None or t["fetch_bytes"] is None:
+        return None
+    if tuning is not None and (tuning["chunk"], tuning["waves_per_block"], tuning["waves_per_cu"]) != t["tuning"]:
         return None
     try:
         if sources_sha1(t["sources"]) != t["sha1"]:
@@ -102,6 +106,14 @@ def parse():
                     help="only run a plain device copy of 1 GiB three times (reference kernel "
                          "for scaling the HBM byte counters of a profiler run)")
     return ap.parse_args()
+
+
+_T0 = time.perf_counter()
+
+
+def progress(leg):
+    """One line on stderr when a leg ends (the JSON line stays on stdout)."""
+    print(f"bench: {leg} done at {time.perf_counter() - _T0:.0f} s", file=sys.stderr, flush=True)
 
 
 def nearest_rank(x, q):
@@ -610,7 +622,7 @@ def main():
                    "clustered_fraction": 0.5, "spheres": 2000, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
-                     "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
+                     "traffic": measured_traffic(tuning), "traffic_unit": "bytes/launch",
                      "kernel": kname, "kernel_ms": k_ms,
                      "flops_per_interaction": flops},
         "tuning": tuning,
@@ -624,6 +636,7 @@ def main():
         / (k_ms * 1e-3) / FP32_VECTOR_PEAK,
         "lists": {k: int(st[k]) for k in ("nleaf", "nblock", "nrange", "nitem")},
     }
+    progress("headline")
     if not args.no_cpu_baseline:
         base, errs, targets, ref = cpu_baseline(box, acc.cpu().numpy(), args.cpu_seconds)
         out["cpu_baseline"] = base
@@ -643,25 +656,33 @@ def main():
             "vs_polynomial_kernel": k_ms / t_ms,
             "error_vs_oracle": sample_errors(acc.cpu().numpy(), targets, ref)}
         plan.set_tuning(variant=0)
+        progress("cpu baseline and split table")
     out["pm_long_range"] = bench_pm(box, pos, mass, 128, max(3, min(args.steps, 10)),
                                     with_error=not args.no_cpu_baseline)
+    progress("PM")
     if not args.no_extras:
         out["monopoles"] = bench_monopoles(plan, box, pos, mass)
+        progress("monopoles")
         kdk = bench_kdk(box, pos, mass, acc)
         reuse = bench_kdk(box, pos, mass, acc, skin=0.2 * box.params.rcut)
         kdk["list_reuse"] = {k: reuse[k] for k in ("skin", "ms_per_top_step", "list_builds_per_top_step",
                                                    "force_evaluations_per_top_step")}
         kdk["list_reuse"]["speedup"] = kdk["ms_per_top_step"] / reuse["ms_per_top_step"]
         out["kdk_adaptive"] = kdk
+        progress("adaptive KDK")
         out["small_box"] = bench_small_box()
+        progress("small box")
     del plan, pos, mass, acc
     torch.cuda.empty_cache()
     if not args.no_large:
         out["precision_16.8M"] = bench_precision()
+        progress("16.8M precision")
         out["large_134M"] = bench_large()
+        progress("134M")
     if not args.no_batched:
         out["batched_vs_per_box"] = bench_batched(max(1, min(args.steps, 5)), 1,
                                                   tune=not args.no_tune)
+        progress("batched")
     print(json.dumps(out), flush=True)
 
 
