@@ -2,9 +2,9 @@
 
 NOT AN ORACLE.  This restates, in FP64 numpy, the acceptance decisions the
 library's list builder takes: 64-particle target blocks cut at 2 r_cut
-extent, source groups of 8 consecutive tree nodes above the leaves, nodes
-of level 2 and up, and the same FP64 operation sequence for the geometric
-and relative tests.  It is used only to check that the library takes the
+extent, source nodes of every level of the hierarchy over the leaves
+(single leaves, groups of 8 consecutive leaves, and up), and the same FP64
+operation sequence for the geometric and relative tests.  It is used only to check that the library takes the
 decisions it is designed to take (the (target, monopole) pair counts match
 exactly); the accuracy of the monopole forces is checked against the exact
 pair sum and the octree dual tree traversal of oracle/tree.py instead.
