@@ -82,9 +82,15 @@ ItemArgs item_args(const BatchDev& bd, const Work& w) {
 
 // Items are laid out so that the 8 XCDs (which take workgroups round-robin)
 // each see one contiguous stretch of items: neighbouring target blocks share
-// most of their sources, which then stay in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
-    return (bid & 7) * per_xcd + (bid >> 3);
+// most of their sources, which then stay in that XCD's L2.  The grid is
+// sized for the item capacity, which may exceed the count: a workgroup past
+// its XCD's stretch gets -1 (mapping it into the next stretch would run
+// that item twice).
+__device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t nitem) {
+    const int64_t per_xcd = (nitem + 7) / 8;
+    const int64_t k = bid >> 3;
+    const int64_t item = (bid & 7) * per_xcd + k;
+    return k < per_xcd && item < nitem ? item : -1;
 }
 
 __device__ __forceinline__ int64_t find_range(const int32_t* __restrict__ rpre, int64_t lo,
@@ -94,6 +100,25 @@ __device__ __forceinline__ int64_t find_range(const int32_t* __restrict__ rpre, 
         const int64_t mid = (lo + hi + 1) >> 1;
         if (rpre[mid] <= p) lo = mid;
         else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The same search by a whole wave, for a wave-uniform p: each round reads
+// 64 evenly spaced entries and keeps the stretch between two of them, so
+// the dependent loads number log_64 of the range count instead of log_2.
+__device__ __forceinline__ int64_t find_range_wave(const int32_t* __restrict__ rpre, int64_t lo,
+                                                   int64_t hi, int32_t p) {
+    const int lane = threadIdx.x & 63;
+    while (lo < hi) {
+        const int64_t stride = (hi - lo + 64) / 64;   // ceil((hi - lo + 1) / 64)
+        const int64_t q = lo + lane * stride;
+        const bool le = q <= hi && rpre[q] <= p;
+        const int c = __popcll(__ballot(le));        // >= 1: rpre[lo] <= p
+        lo += (int64_t)(c - 1) * stride;
+        const int64_t top = lo + stride - 1;
+        hi = top < hi ? top : hi;
+        if (stride == 1) break;
     }
     return lo;
 }
@@ -209,12 +234,14 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 }
 
 // One work item of the FP32 PP kernel on one wave (target block, chunk of
-// its source list).  Sources are fetched 64 list positions at a time: each
-// lane maps its position to a particle through the block's ranges (no
-// search when the window lies in one range, else a binary search bounded to
-// 64 ranges from the wave's range cursor) and loads the FP64 position and
-// the mass; the loads of the next window are issued before the current tile
-// is swept.  A fetched source is shifted by its periodic image, made
+// its source list).  Sources are fetched 64 list positions at a time: the
+// wave reads the 64 ranges from its range cursor on (one per lane), marks in
+// LDS the window positions where one of them starts, and each lane takes its
+// position's range from the count of marks up to it and the range's first
+// particle from the lane that read it; only a window that runs past those
+// 64 ranges falls back to a binary search per lane.  Then each lane loads
+// the FP64 position and the mass; the loads of the next window are issued
+// before the current tile is swept.  A fetched source is shifted by its periodic image, made
 // relative to the FP64 block centre, scaled by 1/ell and rounded to FP32,
 // and dropped if it lies at r_cut or more from each of the four boxes
 // around the block's runs of 16 targets.  Survivors are compacted with a
@@ -232,9 +259,10 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
                                         const double* __restrict__ pos_s,
                                         const float* __restrict__ mass_s, int64_t N,
                                         float* __restrict__ partial,
-                                        unsigned long long* __restrict__ counters, float4* tile_all,
+                                        unsigned long long& n_eval, unsigned long long& n_lane,
+                                        float4* tile_all,
                                         const float4* __restrict__ tab, float4* qb_all,
-                                        double* red) {
+                                        double* red, int* mark_all) {
     constexpr bool NEWTON = (VAR & 1) != 0;
     constexpr bool KAHAN = (VAR & 2) == 0;
     constexpr bool LOCAL = (VAR & 4) == 0;     // FP64 block-centre subtraction
@@ -319,7 +347,8 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     int count = 0;                                   // staged sources (wave-uniform)
     int64_t staged = 0;
     const int32_t first = s0 + wv * kBlock;          // this wave's first window
-    int64_t rcur = s1 > first ? find_range(ia.rpre, r_lo, r_hi, first) : r_lo;
+    int64_t rcur = s1 > first ? find_range_wave(ia.rpre, r_lo, r_hi, first) : r_lo;
+    int* mark = mark_all + wv * kBlock;
 
     double px = 0, py = 0, pz = 0;
     float pm = 0.f;
@@ -328,16 +357,45 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
     auto fetch = [&](int32_t base) {
         const int32_t p = base + lane;
         pv = p < s1;
-        int64_t r = rcur;
-        const int32_t end_cur = rcur < r_hi ? ia.rpre[rcur + 1] : S;
-        if (base + kBlock > end_cur) {
-            // the window starts at most K * 64 positions (so ranges) past the cursor's
+        const int32_t last = s1 - 1 < base + kBlock - 1 ? s1 - 1 : base + kBlock - 1;
+        // the ranges rcur .. rcur + 63, one per lane
+        const int64_t rq = rcur + lane;
+        const bool rv = rq <= r_hi;
+        const int32_t qpre = rv ? ia.rpre[rq] : INT32_MAX;
+        const int32_t qbeg = rv ? ia.rbeg[rq] : 0;
+        const int qcode = rv ? (int)ia.rcode[rq] : 13;
+        // ranges that start at or before the window's first (last) position
+        const int c0 = __popcll(__ballot(qpre <= base));
+        const int c1 = __popcll(__ballot(qpre <= last));
+        int64_t r;
+        int32_t rb, rp;
+        int code;
+        if (c1 < kBlock || rcur + (kBlock - 1) >= r_hi) {
+            // every range of the window was read: mark where they start
+            mark[lane] = 0;
+            wave_sync();
+            if (qpre > base && qpre <= last) mark[qpre - base] = 1;
+            wave_sync();
+            const uint64_t starts = __ballot(mark[lane] != 0);
+            wave_sync();
+            const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+            const int idx = c0 - 1 + __popcll(starts & upto);
+            rb = __shfl(qbeg, idx);
+            rp = __shfl(qpre, idx);
+            code = __shfl(qcode, idx);
+            r = rcur + idx;
+        } else {
+            // more than 64 ranges in reach: the window starts at most K * 64
+            // positions (so ranges) past the cursor's
             const int64_t top = rcur + K * kBlock < r_hi ? rcur + K * kBlock : r_hi;
-            if (pv) r = find_range(ia.rpre, rcur, top, p);
+            r = pv ? find_range(ia.rpre, rcur, top, p) : rcur;
+            rb = ia.rbeg[r];
+            rp = ia.rpre[r];
+            code = ia.rcode[r];
         }
         if (pv) {
-            const int64_t j = (int64_t)ia.rbeg[r] + (p - ia.rpre[r]);
-            pc = ia.rcode[r];
+            const int64_t j = (int64_t)rb + (p - rp);
+            pc = code;
             px = pos_s[j];
             py = pos_s[N + j];
             pz = pos_s[2 * N + j];
@@ -429,10 +487,8 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
             for (int q = 0; q < count; ++q) pair_f32<NEWTON, TABLE>(tile[q], xi, yi, zi, P, ax, ay, az, tab);
         }
     }
-    if (counters && lane == 0) {
-        atomicAdd(counters, (unsigned long long)staged * (unsigned long long)nt);
-        atomicAdd(counters + 1, (unsigned long long)staged * (unsigned long long)kBlock);
-    }
+    n_eval += (unsigned long long)staged * (unsigned long long)nt;
+    n_lane += (unsigned long long)staged * (unsigned long long)kBlock;
     // the compensated sums, then (K > 1) the waves' sums in wave order
     double sx = (double)ax - (double)cx, sy = (double)ay - (double)cy, sz = (double)az - (double)cz;
     if (K > 1) {
@@ -604,15 +660,21 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_kernel(ItemArgs 
     __shared__ float4 qb[K * 8];
     __shared__ double red[K > 1 ? K * 3 * kBlock : 1];
     __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
+    __shared__ int mark[K * kBlock];
     if (ia.sizes[kSkip]) return;
     const int64_t nitem = ia.sizes[kNItem];
-    const int64_t item = xcd_item(blockIdx.x, (nitem + 7) / 8);
-    if (item >= nitem) return;
+    const int64_t item = xcd_item(blockIdx.x, nitem);
+    if (item < 0) return;
     if (VAR & 8) {
         for (int k = threadIdx.x; k < kTabN; k += 64 * K) tab[k] = ia.split_tab[k];
         __syncthreads();
     }
-    pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab, qb, red);
+    unsigned long long n_eval = 0, n_lane = 0;
+    pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, n_eval, n_lane, tile, tab, qb, red, mark);
+    if (counters && (threadIdx.x & (kBlock - 1)) == 0) {
+        atomicAdd(counters, n_eval);
+        atomicAdd(counters + 1, n_lane);
+    }
 }
 
 // Persistent form: a fixed grid of waves pulls items from 8 queues (one
@@ -631,6 +693,7 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
     __shared__ float4 qb[K * 8];
     __shared__ double red[K > 1 ? K * 3 * kBlock : 1];
     __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
+    __shared__ int mark[K * kBlock];
     __shared__ unsigned next_item;
     if (ia.sizes[kSkip]) return;
     if (VAR & 8) {
@@ -640,27 +703,43 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
     const int64_t nitem = ia.sizes[kNItem];
     const int64_t per = (nitem + 7) / 8;
     const int my = blockIdx.x & 7;
+    // the kernel counters, summed over this wave's items and added once
+    unsigned long long n_eval = 0, n_lane = 0;
     for (int v = 0; v < 8; ++v) {
         const int q = (my + v) & 7;
         const int64_t qbeg = q * per;
         const int64_t qend = qbeg + per < nitem ? qbeg + per : nitem;
         if (qbeg >= qend) continue;
+        const unsigned qlen = (unsigned)(qend - qbeg);
         for (;;) {
+            // a pop; a queue already seen empty is left without one, so the
+            // waves that drain the queues at the end do not line up on its
+            // counter (the counter only grows: a stale read is never too big)
             unsigned i = 0;
             if (K == 1) {
-                if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
+                if (threadIdx.x == 0) {
+                    const unsigned seen = __hip_atomic_load(&queues[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    i = seen >= qlen ? seen : atomicAdd(&queues[q], 1u);
+                }
                 i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
             } else {
                 // one pop per workgroup, shared through LDS
                 __syncthreads();
-                if (threadIdx.x == 0) next_item = atomicAdd(&queues[q], 1u);
+                if (threadIdx.x == 0) {
+                    const unsigned seen = __hip_atomic_load(&queues[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    next_item = seen >= qlen ? seen : atomicAdd(&queues[q], 1u);
+                }
                 __syncthreads();
                 i = next_item;
             }
-            const int64_t item = qbeg + (int64_t)i;
-            if (item >= qend) break;
-            pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, counters, tile, tab, qb, red);
+            if (i >= qlen) break;
+            pp_item<VAR, K>(ia, qbeg + (int64_t)i, pos_s, mass_s, N, partial, n_eval, n_lane, tile, tab, qb,
+                            red, mark);
         }
+    }
+    if (counters && (threadIdx.x & (kBlock - 1)) == 0 && n_lane) {
+        atomicAdd(counters, n_eval);
+        atomicAdd(counters + 1, n_lane);
     }
 }
 
@@ -733,8 +812,8 @@ __global__ void __launch_bounds__(64) pp_f64_kernel(ItemArgs ia, const double* _
                                                     int32_t* __restrict__ pcount) {
     if (ia.sizes[kSkip]) return;
     const int64_t nitem = ia.sizes[kNItem];
-    const int64_t item = xcd_item(blockIdx.x, (nitem + 7) / 8);
-    if (item >= nitem) return;
+    const int64_t item = xcd_item(blockIdx.x, nitem);
+    if (item < 0) return;
     const int lane = threadIdx.x;
     const int32_t b = ia.iblock[item];
     const int32_t s0 = ia.is0[item];

@@ -165,6 +165,31 @@ def test_launch_shapes_agree(pp, tuning):
         assert np.array_equal(got, base)
 
 
+def test_kernel_counters_agree_across_launch_shapes(pp):
+    """Every work item runs exactly once in every launch shape: the
+    kernel's counters of evaluated pairs and lane-pairs (sums over the
+    sources each item stages) do not depend on the chunk, the waves per
+    block or the launch form, and bound the interaction count from above."""
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    p, m = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
+    plan.accel(p, m)
+    inter = plan.count_interactions()
+    seen = set()
+    for t in [dict(chunk=2048, waves_per_block=1, persistent=0), dict(chunk=256, waves_per_block=1, persistent=0),
+              dict(chunk=256, waves_per_block=1, persistent=1, waves_per_cu=12),
+              dict(chunk=1024, waves_per_block=2, persistent=1, waves_per_cu=20),
+              dict(chunk=4096, waves_per_block=4, persistent=0),
+              dict(chunk=4096, waves_per_block=4, persistent=1, waves_per_cu=32)]:
+        plan.set_tuning(use_graph=0, **t)
+        plan.accel(p, m)
+        torch.cuda.synchronize()
+        st = plan.stats()
+        seen.add((st["evaluated"], st["lane_pairs"]))
+        assert inter <= st["evaluated"] <= st["lane_pairs"], t
+    assert len(seen) == 1, seen
+
+
 @pytest.mark.parametrize("k,persistent", [(2, 1), (4, 1), (4, 0)])
 def test_waves_per_block_vs_oracle(pp, oracle_mod, k, persistent):
     """K waves sharing a target block: the oracle's tolerances on the 32k
