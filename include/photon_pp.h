@@ -269,7 +269,7 @@ int pp_plan_set_timing(pp_plan* plan, int on);
  *               table in LDS (128 quadratic pieces, the form sec. 3.1
  *               describes) instead of the polynomial.  0 is the production
  *               kernel.
- *  waves_per_block  1, 2 or 4: waves sharing one work item.  A target block
+ *  waves_per_block  1, 2, 4 or 8: waves sharing one work item.  A target block
  *               (the i tile: up to 64 targets, one per lane) is swept by
  *               waves_per_block waves, wave k taking the windows k, k + K,
  *               ... of 64 source-list positions of the item (the j tiles);
@@ -291,9 +291,10 @@ int pp_plan_set_tuning(pp_plan* plan, const pp_tuning* t);
 /* Autotuner: times the PP stage (HIP events around the queue reset, the PP
  * kernel or its graph and the reduction; median of 3 after a warm run) on
  * the given particles and keeps the fastest tuning in the plan.  First the
- * tiles: 1024, 2048 or 4096 source-list positions per wave with 1, 2 or 4
+ * tiles: 1024, 2048 or 4096 source-list positions per wave with 1, 2, 4 or 8
  * waves per target block (chunk = positions x waves_per_block), persistent
- * at 20 waves per CU; then, at the best tiles, the launch shape: persistent
+ * at 20 waves per CU, and 256 or 512 positions too when the lists hold
+ * fewer than 2^24 positions in all (small boxes); then, at the best tiles, the launch shape: persistent
  * with 12, 24 or 32 waves per CU, or one workgroup per item.  The variant is
  * kept.  With cache_path (may be NULL) the choice is looked up first and
  * stored afterwards, one line "arch/nbox<k>/n2^<j>/leaf<m> chunk persistent
@@ -336,7 +337,7 @@ int pp_plan_lists_export(const pp_plan* plan, int32_t* perm, int32_t* bstart, in
                          int32_t* blo, int32_t* bhi, int64_t* roff, int32_t* slen, int32_t* rbeg,
                          int32_t* rpre, uint8_t* rcode);
 
-/* ------------------------------------------------------------- batches --/* ------------------------------------------------------------- batches --
+/* ------------------------------------------------------------- batches --
  * Many independent periodic boxes of different N, L and split parameters in
  * one pass (the task-queue idea of sec. 4.3 taken to whole boxes): every
  * stage runs once over all boxes, and the PP kernel is one persistent,

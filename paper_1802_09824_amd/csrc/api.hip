@@ -594,7 +594,7 @@ struct Batch {
         // 1) the j tile: source-list positions per wave, and K waves per
         //    target block (a block's i tile of 64 targets swept by K waves),
         //    persistent at 20 waves per CU
-        const int ks[] = {1, 2, 4};
+        const int ks[] = {1, 2, 4, 8};
         for (int c : {1024, 2048, 4096})
             for (int k : ks) {
                 if (k > 1 && !multi) continue;
@@ -638,7 +638,8 @@ struct Batch {
                t.waves_per_cu <= 64 && !(t.use_graph && !t.persistent) && t.variant >= 0 &&
                t.variant <= 15 &&
                (t.waves_per_block == 1 ||
-                ((t.waves_per_block == 2 || t.waves_per_block == 4) && (t.variant == 0 || t.variant == 8)));
+                ((t.waves_per_block == 2 || t.waves_per_block == 4 || t.waves_per_block == 8) &&
+                 (t.variant == 0 || t.variant == 8)));
     }
 
     int set_timing(int on) {
@@ -661,8 +662,8 @@ static int check_tuning(const pp_tuning* t) {
     if (t->waves_per_cu < 1 || t->waves_per_cu > 64) return fail(PP_EINVAL, "waves_per_cu in 1..64");
     if (t->use_graph && !t->persistent) return fail(PP_EINVAL, "graph replay needs the persistent kernel");
     if (t->variant < 0 || t->variant > 15) return fail(PP_EINVAL, "variant must be in 0..15");
-    if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
-        return fail(PP_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4 && t->waves_per_block != 8)
+        return fail(PP_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
     if (t->waves_per_block > 1 && t->variant != 0 && t->variant != 8)
         return fail(PP_EINVAL, "more than one wave per block needs variant 0 or 8");
     return PP_OK;

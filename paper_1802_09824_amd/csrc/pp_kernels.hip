@@ -1037,6 +1037,8 @@ int launch_pp_f32(const BatchDev& bd, const Work& w, int waves_per_block, Mode m
         return launch_pp_f32_k<2>(ia, w, mode, waves_per_cu, variant & 15, partial, counters, queues, s);
     if (waves_per_block == 4)
         return launch_pp_f32_k<4>(ia, w, mode, waves_per_cu, variant & 15, partial, counters, queues, s);
+    if (waves_per_block == 8)
+        return launch_pp_f32_k<8>(ia, w, mode, waves_per_cu, variant & 15, partial, counters, queues, s);
     switch (variant & 15) {
         case 0: return launch_pp_f32_var<0, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);
         case 1: return launch_pp_f32_var<1, 1>(ia, w, mode, waves_per_cu, partial, counters, queues, s);

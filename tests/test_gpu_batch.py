@@ -148,7 +148,10 @@ def test_graph_recaptured_after_smaller_n(pp):
                                     dict(waves_per_block=2), dict(waves_per_block=4, chunk=8192),
                                     dict(waves_per_block=4, chunk=256, persistent=0),
                                     dict(waves_per_block=2, persistent=1, use_graph=1, waves_per_cu=7),
-                                    dict(waves_per_block=4, variant=8)])
+                                    dict(waves_per_block=4, variant=8),
+                                    dict(waves_per_block=8, chunk=8192),
+                                    dict(waves_per_block=8, chunk=512, persistent=0),
+                                    dict(waves_per_block=8, persistent=1, use_graph=1, waves_per_cu=24)])
 def test_launch_shapes_agree(pp, tuning):
     b = W.make_config(1)
     plan = pp.Plan(b.params, b.n)
@@ -180,7 +183,8 @@ def test_kernel_counters_agree_across_launch_shapes(pp):
               dict(chunk=256, waves_per_block=1, persistent=1, waves_per_cu=12),
               dict(chunk=1024, waves_per_block=2, persistent=1, waves_per_cu=20),
               dict(chunk=4096, waves_per_block=4, persistent=0),
-              dict(chunk=4096, waves_per_block=4, persistent=1, waves_per_cu=32)]:
+              dict(chunk=4096, waves_per_block=4, persistent=1, waves_per_cu=32),
+              dict(chunk=8192, waves_per_block=8, persistent=1, waves_per_cu=24)]:
         plan.set_tuning(use_graph=0, **t)
         plan.accel(p, m)
         torch.cuda.synchronize()
@@ -190,7 +194,7 @@ def test_kernel_counters_agree_across_launch_shapes(pp):
     assert len(seen) == 1, seen
 
 
-@pytest.mark.parametrize("k,persistent", [(2, 1), (4, 1), (4, 0)])
+@pytest.mark.parametrize("k,persistent", [(2, 1), (4, 1), (4, 0), (8, 1)])
 def test_waves_per_block_vs_oracle(pp, oracle_mod, k, persistent):
     """K waves sharing a target block: the oracle's tolerances on the 32k
     box and on a ragged clustered box with lists spanning several items."""
@@ -199,7 +203,7 @@ def test_waves_per_block_vs_oracle(pp, oracle_mod, k, persistent):
                     mass=np.random.default_rng(42).uniform(0.5, 1.5, 9001).astype(np.float32),
                     params=BoxParams.from_mesh(40.0, 20), name="ragged")):
         plan = pp.Plan(b.params, b.n)
-        plan.set_tuning(waves_per_block=k, persistent=persistent, chunk=256 * k)
+        plan.set_tuning(waves_per_block=k, persistent=persistent, chunk=256 * min(k, 4))
         acc = plan.accel(dev(b.pos, torch.float64), dev(b.mass, torch.float32)).cpu().numpy()
         assert plan.stats()["nitem"] > plan.stats()["nblock"]
         ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, pair_abs=True)
@@ -227,7 +231,8 @@ def test_tuning_validation(pp):
     b = W.make_config(1)
     plan = pp.Plan(b.params, b.n)
     for bad in [dict(chunk=100), dict(chunk=0), dict(waves_per_cu=0), dict(use_graph=1, persistent=0),
-                dict(waves_per_block=3), dict(waves_per_block=0), dict(waves_per_block=2, variant=1)]:
+                dict(waves_per_block=3), dict(waves_per_block=0), dict(waves_per_block=16),
+                dict(waves_per_block=2, variant=1), dict(waves_per_block=8, variant=4)]:
         with pytest.raises(pp.PPError):
             plan.set_tuning(**{**dict(chunk=4096, persistent=0, waves_per_cu=16, use_graph=0), **bad})
 
