@@ -234,12 +234,13 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 }
 
 // One work item of the FP32 PP kernel on one wave (target block, chunk of
-// its source list).  Sources are fetched 64 list positions at a time: the
-// wave reads the 64 ranges from its range cursor on (one per lane), marks in
-// LDS the window positions where one of them starts, and each lane takes its
-// position's range from the count of marks up to it and the range's first
-// particle from the lane that read it; only a window that runs past those
-// 64 ranges falls back to a binary search per lane.  Then each lane loads
+// its source list).  Sources are fetched 64 list positions at a time.  A
+// window inside the range at the wave's range cursor needs no mapping;
+// otherwise the wave reads the 64 ranges from the cursor on (one per lane),
+// marks in LDS the window positions where one of them starts, and each lane
+// takes its position's range from the count of marks up to it and the
+// range's first particle from the lane that read it; only a window that
+// runs past those 64 ranges falls back to a binary search per lane.  Then each lane loads
 // the FP64 position and the mass; the loads of the next window are issued
 // before the current tile is swept.  A fetched source is shifted by its periodic image, made
 // relative to the FP64 block centre, scaled by 1/ell and rounded to FP32,
@@ -358,40 +359,49 @@ __device__ __forceinline__ void pp_item(const ItemArgs& ia, int64_t item,
         const int32_t p = base + lane;
         pv = p < s1;
         const int32_t last = s1 - 1 < base + kBlock - 1 ? s1 - 1 : base + kBlock - 1;
-        // the ranges rcur .. rcur + 63, one per lane
-        const int64_t rq = rcur + lane;
-        const bool rv = rq <= r_hi;
-        const int32_t qpre = rv ? ia.rpre[rq] : INT32_MAX;
-        const int32_t qbeg = rv ? ia.rbeg[rq] : 0;
-        const int qcode = rv ? (int)ia.rcode[rq] : 13;
-        // ranges that start at or before the window's first (last) position
-        const int c0 = __popcll(__ballot(qpre <= base));
-        const int c1 = __popcll(__ballot(qpre <= last));
         int64_t r;
         int32_t rb, rp;
         int code;
-        if (c1 < kBlock || rcur + (kBlock - 1) >= r_hi) {
-            // every range of the window was read: mark where they start
-            mark[lane] = 0;
-            wave_sync();
-            if (qpre > base && qpre <= last) mark[qpre - base] = 1;
-            wave_sync();
-            const uint64_t starts = __ballot(mark[lane] != 0);
-            wave_sync();
-            const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
-            const int idx = c0 - 1 + __popcll(starts & upto);
-            rb = __shfl(qbeg, idx);
-            rp = __shfl(qpre, idx);
-            code = __shfl(qcode, idx);
-            r = rcur + idx;
+        const int32_t end_cur = rcur < r_hi ? ia.rpre[rcur + 1] : S;
+        if (last < end_cur) {
+            // the cursor's range holds the whole window: nothing to map
+            r = rcur;
+            rb = ia.rbeg[rcur];
+            rp = ia.rpre[rcur];
+            code = ia.rcode[rcur];
         } else {
-            // more than 64 ranges in reach: the window starts at most K * 64
-            // positions (so ranges) past the cursor's
-            const int64_t top = rcur + K * kBlock < r_hi ? rcur + K * kBlock : r_hi;
-            r = pv ? find_range(ia.rpre, rcur, top, p) : rcur;
-            rb = ia.rbeg[r];
-            rp = ia.rpre[r];
-            code = ia.rcode[r];
+            // the ranges rcur .. rcur + 63, one per lane
+            const int64_t rq = rcur + lane;
+            const bool rv = rq <= r_hi;
+            const int32_t qpre = rv ? ia.rpre[rq] : INT32_MAX;
+            const int32_t qbeg = rv ? ia.rbeg[rq] : 0;
+            const int qcode = rv ? (int)ia.rcode[rq] : 13;
+            // ranges that start at or before the window's first (last) position
+            const int c0 = __popcll(__ballot(qpre <= base));
+            const int c1 = __popcll(__ballot(qpre <= last));
+            if (c1 < kBlock || rcur + (kBlock - 1) >= r_hi) {
+                // every range of the window was read: mark where they start
+                mark[lane] = 0;
+                wave_sync();
+                if (qpre > base && qpre <= last) mark[qpre - base] = 1;
+                wave_sync();
+                const uint64_t starts = __ballot(mark[lane] != 0);
+                wave_sync();
+                const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+                const int idx = c0 - 1 + __popcll(starts & upto);
+                rb = __shfl(qbeg, idx);
+                rp = __shfl(qpre, idx);
+                code = __shfl(qcode, idx);
+                r = rcur + idx;
+            } else {
+                // more than 64 ranges in reach: the window starts at most K * 64
+                // positions (so ranges) past the cursor's
+                const int64_t top = rcur + K * kBlock < r_hi ? rcur + K * kBlock : r_hi;
+                r = pv ? find_range(ia.rpre, rcur, top, p) : rcur;
+                rb = ia.rbeg[r];
+                rp = ia.rpre[r];
+                code = ia.rcode[r];
+            }
         }
         if (pv) {
             const int64_t j = (int64_t)rb + (p - rp);
@@ -712,23 +722,14 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
         if (qbeg >= qend) continue;
         const unsigned qlen = (unsigned)(qend - qbeg);
         for (;;) {
-            // a pop; a queue already seen empty is left without one, so the
-            // waves that drain the queues at the end do not line up on its
-            // counter (the counter only grows: a stale read is never too big)
             unsigned i = 0;
             if (K == 1) {
-                if (threadIdx.x == 0) {
-                    const unsigned seen = __hip_atomic_load(&queues[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    i = seen >= qlen ? seen : atomicAdd(&queues[q], 1u);
-                }
+                if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
                 i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
             } else {
                 // one pop per workgroup, shared through LDS
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    const unsigned seen = __hip_atomic_load(&queues[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    next_item = seen >= qlen ? seen : atomicAdd(&queues[q], 1u);
-                }
+                if (threadIdx.x == 0) next_item = atomicAdd(&queues[q], 1u);
                 __syncthreads();
                 i = next_item;
             }
