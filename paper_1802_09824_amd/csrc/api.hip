@@ -250,7 +250,7 @@ struct Batch {
         PP_TRY(w.bad.reserve(64));
         PP_TRY(w.misc.reserve(64));
         PP_TRY(counters.reserve(64));
-        PP_TRY(queues.reserve(64));
+        PP_TRY(queues.reserve(kQueueBytes));
         return PP_OK;
     }
 

@@ -78,6 +78,11 @@ int read_back(const T* dev, T* host, hipStream_t s) {
 // inside one kBlock-particle chunk of one box whose bounding box side stays
 // within 2 r_cut (so FP32 offsets from the block centre stay small).
 constexpr int kBlock = 64;
+// The persistent kernel's 8 work queues (one per XCD), each counter on its
+// own 256-byte stretch so that pops on different queues do not contend for
+// one cache line.
+constexpr int kQueueStride = 64;
+constexpr size_t kQueueBytes = 8 * kQueueStride * sizeof(unsigned);
 
 // Integer bounding box of grid cells, hi exclusive.  Grid units: the box is
 // W = 2^b cells wide, coordinates fit int32.

@@ -724,12 +724,12 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
         for (;;) {
             unsigned i = 0;
             if (K == 1) {
-                if (threadIdx.x == 0) i = atomicAdd(&queues[q], 1u);
+                if (threadIdx.x == 0) i = atomicAdd(&queues[q * kQueueStride], 1u);
                 i = (unsigned)__builtin_amdgcn_readfirstlane((int)i);
             } else {
                 // one pop per workgroup, shared through LDS
                 __syncthreads();
-                if (threadIdx.x == 0) next_item = atomicAdd(&queues[q], 1u);
+                if (threadIdx.x == 0) next_item = atomicAdd(&queues[q * kQueueStride], 1u);
                 __syncthreads();
                 i = next_item;
             }
@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_persistent(ItemA
 
 // Clears the work queues and (when given) the three kernel counters.
 __global__ void reset_queues_kernel(unsigned* q, unsigned long long* ctr) {
-    if (q && threadIdx.x < 8) q[threadIdx.x] = 0u;
+    if (q && threadIdx.x < 8) q[threadIdx.x * kQueueStride] = 0u;
     if (ctr && threadIdx.x < 3) ctr[threadIdx.x] = 0ull;
 }
 
