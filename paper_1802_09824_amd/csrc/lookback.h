@@ -5,7 +5,10 @@
 // A workgroup takes its tile number from a ticket counter, so every tile it
 // may wait for has already started and publishes without waiting itself.
 // Per summed quantity a tile publishes one 64-bit word: (aggregate << 2) | 1,
-// later (inclusive prefix << 2) | 2; 0 means not yet published.  A word is
+// later (inclusive prefix << 2) | 2; 0 means not yet published.  The ticket
+// and every word sit on cache lines of their own (kLbWordStride words
+// apart), so that a tile's publishes and its neighbours' polls do not
+// contend for one line.  A word is
 // read and written whole by agent-scope atomics, so a value and its flag are
 // never seen apart.  The workspace holds two regions (a ticket, then the
 // words), used by consecutive kernels in turn: a region is zero when a
@@ -19,6 +22,7 @@
 namespace pp {
 
 constexpr int kLbSpins = 1 << 22;
+constexpr int kLbWordStride = 16;
 
 // One kernel's share of the workspace: its region (ticket, then words) and
 // the region it clears.
@@ -54,7 +58,7 @@ __device__ int64_t lb_walk_back(const unsigned long long* words, int64_t tile, i
         unsigned long long w = 2ull;
         if (k >= 0) {
             for (int spin = 0;; ++spin) {
-                w = __hip_atomic_load(words + k * NV + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                w = __hip_atomic_load(words + (k * NV + c) * kLbWordStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (w & 3ull) break;
                 if (spin > kLbSpins) {
                     if (sizes) atomicOr(reinterpret_cast<unsigned long long*>(sizes + kOverflow), 64ull);
@@ -79,8 +83,8 @@ __device__ int64_t lb_walk_back(const unsigned long long* words, int64_t tile, i
 template <int NV>
 __device__ int64_t lb_tile_prefix(const LbArgs& lb, int64_t tile, int c, int64_t agg, int64_t* sizes,
                                   int lane) {
-    unsigned long long* words = lb.cur + 1;
-    unsigned long long* w = words + tile * NV + c;
+    unsigned long long* words = lb.cur + kLbWordStride;
+    unsigned long long* w = words + (tile * NV + c) * kLbWordStride;
     if (tile == 0) {
         if (lane == 0) lb_publish(w, agg, 2u);
         return 0;
@@ -92,7 +96,8 @@ __device__ int64_t lb_tile_prefix(const LbArgs& lb, int64_t tile, int c, int64_t
 }
 
 // Host side (scan.hip): makes the workspace hold two regions of at least
-// `words` words plus the ticket each (fresh memory is cleared on s).
+// `words` words plus the ticket each, a line apart (fresh memory is cleared
+// on s).
 int grow_lookback(DevBuf& ws, int64_t words, hipStream_t s);
 // The regions of the next kernel that uses the workspace, which must hold
 // `words` words per region (grown beforehand); flips the region for the

@@ -170,14 +170,15 @@ int launch(const ScanIO& io, int64_t n, DevBuf& ws, hipStream_t s, int64_t* size
 }  // namespace
 
 int scan_workspace(int64_t n, size_t* bytes) {
-    // two regions of a ticket and the words
-    *bytes = 2 * sizeof(unsigned long long) * (size_t)(1 + words_for(n) + 2);
+    // two regions of a ticket and the words, a line each
+    *bytes = 2 * sizeof(unsigned long long) * (size_t)(1 + (words_for(n) + 1) * kLbWordStride + 2);
     return PP_OK;
 }
 
 int grow_scan(DevBuf& buf, int64_t n, hipStream_t s) { return grow_lookback(buf, words_for(n), s); }
 
 int lookback_args(DevBuf& ws, int64_t words, LbArgs* out) {
+    words = (words + 1) * kLbWordStride;      // the ticket's line, then a line per word
     const int64_t region = (int64_t)(ws.bytes / sizeof(unsigned long long)) / 2;
     if (1 + words > region) return fail(PP_EDEVICE, "look-back workspace smaller than its tiles");
     unsigned long long* base = ws.as<unsigned long long>();
@@ -190,6 +191,7 @@ int lookback_args(DevBuf& ws, int64_t words, LbArgs* out) {
 }
 
 int grow_lookback(DevBuf& buf, int64_t words, hipStream_t s) {
+    words = (words + 1) * kLbWordStride;
     const size_t need = 2 * sizeof(unsigned long long) * (size_t)(1 + words + 2);
     const uint64_t gen = alloc_generation();
     PP_TRY(buf.reserve(need));
