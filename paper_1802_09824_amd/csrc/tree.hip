@@ -1231,11 +1231,13 @@ static int64_t grow_cap(int64_t cap, int64_t need) {
     return need + need / 4 + 1024;
 }
 
-// After a pass that fitted: a capacity far above the need comes down to it
-// (plus the margin).
+// After a pass that fitted: a capacity well above the need comes down to it
+// (plus the margin).  The grids and scans of the list builder span the
+// capacities, so a first guess far above the need (the entry passes start
+// from doublings) would otherwise keep costing time on every call.
 static int64_t settle_cap(int64_t cap, int64_t need) {
     const int64_t want = need + need / 4 + 1024;
-    return cap > 2 * want ? want : cap;
+    return cap > want + want / 2 ? want : cap;
 }
 
 int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_req, Work& w,
