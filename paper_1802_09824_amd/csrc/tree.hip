@@ -1475,7 +1475,9 @@ int lists_to_host(Work& w, hipStream_t s, bool* regrow, bool* moved) {
     w.cap_block = settle_cap(w.cap_block, h[kNeedBlock]);
     for (int p = 0; p < w.npass; ++p) w.cap_ent[p] = settle_cap(w.cap_ent[p], h[kNeedEntry0 + p]);
     w.cap_range = settle_cap(w.cap_range, h[kNeedRange]);
-    w.cap_item = settle_cap(w.cap_item, h[kNeedItem]);
+    // the item count follows the active flags of each call: only a call
+    // over every target brings the item capacity down
+    if (!w.active) w.cap_item = settle_cap(w.cap_item, h[kNeedItem]);
     w.nleaf = h[kNLeaf];
     w.nblock = h[kNBlock];
     w.nentry = h[kNEntry];
