@@ -37,20 +37,42 @@ FLOPS_GENERAL = 39
 PAPER_FLOPS_PER_INTERACTION = 22      # convention of sec. 5 (Newtonian pair count)
 FP32_VECTOR_PEAK = 157.3e12           # MI355X, 256 CU x 2.4 GHz x 256 flop/clk
 # HBM bytes per PP-kernel launch on the headline workload, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes scaled by a plain 1 GiB copy measured the
-# same way (factors below).  Valid only for the kernel sources they were taken
-# on (SHA-1 over the files listed); otherwise the roofline reports null.
+# FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch) scaled by what the same
+# counters read for a plain 1 GiB copy (factors below), one pair of passes
+# per launch shape the autotuner is likely to pick.  Valid only for the
+# kernel sources they were taken on (SHA-1 over the files listed) and for a
+# measured launch shape; otherwise the roofline reports null.
 TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "361885f4548456d40ac93fffbc9e0145db1ae318",
-    "fetch_bytes": 375546195,     # FETCH_SIZE 183376.2 KiB x 1.99996
-    "write_bytes": 196076960,     # WRITE_SIZE 191481.4 KiB x 1.00000
-    "fetch_scale": 1.99996,          # 1 GiB copy: 1048576 KiB / FETCH_SIZE read
-    "write_scale": 1.00000,          # 1 GiB copy: 1048576 KiB / WRITE_SIZE read
-    # the launch shape the counters were taken at (chunk, waves per block, waves per CU)
-    "tuning": (8192, 4, 20),
+    "sha1": "143cd8c9b94ff504b62c1457abf9209b6ac724fd",
+    "fetch_scale": 1.99996,       # 1 GiB copy: 1048576 KiB / 524299.5 KiB of FETCH_SIZE
+    "write_scale": 1.00000,       # 1 GiB copy: 1048576 KiB / 1048576.0 KiB of WRITE_SIZE
+    # (chunk, waves per block, waves per CU (0: one workgroup per item), persistent):
+    # (FETCH_SIZE KiB, WRITE_SIZE KiB) of the timed step's PP dispatch
+    "kib": {
+        (1024, 1, 20, 1): (143044.9, 178276.7),
+        (1024, 1, 24, 1): (163171.4, 178596.7),
+        (1024, 1, 32, 1): (163015.5, 179108.7),
+        (2048, 1, 0, 0): (104940.9, 108831.7),
+        (2048, 1, 20, 1): (182690.5, 106655.2),
+        (2048, 1, 24, 1): (207819.6, 106968.6),
+        (2048, 1, 32, 1): (210948.6, 107481.4),
+        (2048, 2, 32, 1): (137671.8, 106415.8),
+        (4096, 1, 20, 1): (319110.7, 137895.2),
+        (4096, 1, 32, 1): (364703.8, 138528.6),
+        (4096, 2, 32, 1): (198581.8, 138201.0),
+        (4096, 4, 32, 1): (152608.2, 137994.1),
+        (8192, 2, 32, 1): (265121.8, 180833.6),
+        (8192, 4, 0, 0): (117593.1, 190445.6),
+        (8192, 4, 20, 1): (188127.8, 180865.5),
+        (8192, 4, 24, 1): (187394.6, 180913.2),
+        (8192, 4, 32, 1): (187550.4, 181053.9),
+        (8192, 8, 32, 1): (155178.2, 180953.8),
+        (16384, 4, 32, 1): (197927.6, 195678.9),
+        (16384, 8, 32, 1): (161105.2, 195654.8),
+    },
 }
 
 
@@ -63,20 +85,23 @@ def sources_sha1(files):
     return h.hexdigest()
 
 
-def measured_traffic(tuning=None):
-    """HBM bytes per launch of the PP kernel, or None if not measured for
-    the current kernel sources and (when given) this launch shape."""
+def measured_traffic(tuning):
+    """HBM bytes per launch of the PP kernel at this launch shape, or None if
+    the shape was not measured or the kernel sources changed since."""
     t = TRAFFIC
-    if t["sha1"] is None or t["fetch_bytes"] is None:
+    if t["sha1"] is None or t["fetch_scale"] is None:
         return None
-    if tuning is not None and (tuning["chunk"], tuning["waves_per_block"], tuning["waves_per_cu"]) != t["tuning"]:
+    key = (tuning["chunk"], tuning["waves_per_block"], tuning["waves_per_cu"] if tuning["persistent"] else 0,
+           tuning["persistent"])
+    if key not in t["kib"]:
         return None
     try:
         if sources_sha1(t["sources"]) != t["sha1"]:
             return None
     except OSError:
         return None
-    return float(t["fetch_bytes"] + t["write_bytes"])
+    fetch, write = t["kib"][key]
+    return 1024.0 * (fetch * t["fetch_scale"] + write * t["write_scale"])
 
 
 def parse():
@@ -97,9 +122,10 @@ def parse():
                     help="skip the 16.8M precision and 134M large-box legs")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tiles instead of running the autotuner first")
-    ap.add_argument("--tuning", default=None, metavar="CHUNK,WAVES_PER_BLOCK,WAVES_PER_CU",
-                    help="run the headline box with these persistent-kernel tiles instead of "
-                         "autotuning (for profiling runs of a known launch shape)")
+    ap.add_argument("--tuning", default=None, metavar="CHUNK,WAVES_PER_BLOCK,WAVES_PER_CU[,PERSISTENT]",
+                    help="run the headline box with this launch shape instead of autotuning (for "
+                         "profiling runs of a known launch shape); PERSISTENT 0 is one workgroup "
+                         "per item, default 1")
     ap.add_argument("--print-sources-sha1", action="store_true",
                     help="print the SHA-1 of the PP kernel sources the traffic figure is tied to")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -584,9 +610,10 @@ def main():
     acc = torch.empty((3, box.n), dtype=torch.float32, device="cuda")
     plan = pp.Plan(p, box.n)
     if args.tuning:
-        chunk, wpb, wpc = (int(v) for v in args.tuning.split(","))
-        plan.set_tuning(chunk=chunk, persistent=1, waves_per_cu=wpc, use_graph=0, variant=0,
-                        waves_per_block=wpb)
+        v = [int(x) for x in args.tuning.split(",")]
+        chunk, wpb, wpc = v[:3]
+        plan.set_tuning(chunk=chunk, persistent=v[3] if len(v) > 3 else 1, waves_per_cu=wpc, use_graph=0,
+                        variant=0, waves_per_block=wpb)
         tuning = plan.get_tuning()
     else:
         tuning = plan.get_tuning() if args.no_tune else plan.autotune(pos, mass)   # untimed, one-off
