@@ -118,6 +118,8 @@ def parse():
                     help="skip the monopole and adaptive-KDK legs (for profiling runs)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-box batched-vs-per-box comparison (for profiling)")
+    ap.add_argument("--only-small-box", action="store_true",
+                    help="run only the 32k uniform box's whole-step leg (for profiling)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 16.8M precision and 134M large-box legs")
     ap.add_argument("--no-tune", action="store_true",
@@ -602,6 +604,10 @@ def main():
         print(json.dumps({"batched_vs_per_box": bench_batched(max(1, min(args.steps, 5)), 1,
                                                               with_error=False,
                                                               tune=not args.no_tune)}), flush=True)
+        return
+    if args.only_small_box:
+        print(json.dumps({"small_box": bench_small_box(steps=max(1, args.steps), tune=not args.no_tune)}),
+              flush=True)
         return
     box = workloads.make_config(2)
     p = box.params
