@@ -52,25 +52,41 @@ TRAFFIC = {
     # (chunk, waves per block, waves per CU (0: one workgroup per item), persistent):
     # (FETCH_SIZE KiB, WRITE_SIZE KiB) of the timed step's PP dispatch
     "kib": {
+        (1024, 1, 0, 0): (98476.3, 183744.5),
+        (1024, 1, 12, 1): (127413.8, 177636.7),
         (1024, 1, 20, 1): (143044.9, 178276.7),
         (1024, 1, 24, 1): (163171.4, 178596.7),
         (1024, 1, 32, 1): (163015.5, 179108.7),
         (2048, 1, 0, 0): (104940.9, 108831.7),
+        (2048, 1, 12, 1): (137537.7, 106031.5),
         (2048, 1, 20, 1): (182690.5, 106655.2),
         (2048, 1, 24, 1): (207819.6, 106968.6),
         (2048, 1, 32, 1): (210948.6, 107481.4),
+        (2048, 2, 20, 1): (138990.2, 106033.6),
+        (2048, 2, 24, 1): (138700.9, 106158.6),
         (2048, 2, 32, 1): (137671.8, 106415.8),
         (4096, 1, 20, 1): (319110.7, 137895.2),
         (4096, 1, 32, 1): (364703.8, 138528.6),
+        (4096, 2, 20, 1): (201089.8, 137850.3),
+        (4096, 2, 24, 1): (200960.1, 137957.4),
         (4096, 2, 32, 1): (198581.8, 138201.0),
+        (4096, 4, 0, 0): (107042.4, 152060.0),
+        (4096, 4, 12, 1): (142220.3, 137529.4),
+        (4096, 4, 20, 1): (153249.3, 137807.9),
+        (4096, 4, 24, 1): (153924.6, 137868.4),
         (4096, 4, 32, 1): (152608.2, 137994.1),
         (8192, 2, 32, 1): (265121.8, 180833.6),
         (8192, 4, 0, 0): (117593.1, 190445.6),
+        (8192, 4, 12, 1): (155755.4, 180853.3),
         (8192, 4, 20, 1): (188127.8, 180865.5),
         (8192, 4, 24, 1): (187394.6, 180913.2),
         (8192, 4, 32, 1): (187550.4, 181053.9),
+        (8192, 8, 20, 1): (153673.8, 180869.8),
         (8192, 8, 32, 1): (155178.2, 180953.8),
+        (16384, 4, 20, 1): (198121.1, 195508.1),
+        (16384, 4, 24, 1): (197856.8, 195580.6),
         (16384, 4, 32, 1): (197927.6, 195678.9),
+        (16384, 8, 20, 1): (161966.4, 195590.5),
         (16384, 8, 32, 1): (161105.2, 195654.8),
     },
 }
