@@ -252,7 +252,7 @@ struct Work {
     std::vector<int64_t> choff_h;         // chunk offsets of the boxes (host)
     DevBuf choff, ccount, coff;
     DevBuf bstart, bcount, bbox, bboxid;
-    DevBuf fent_a, fent_b, fcnt, foff;
+    DevBuf fent_a, fent_b, fcnt, foff, fmask;
     DevBuf lmask_e, rcnt_e, scnt_e, roff_e, soff_e, eoff;
     DevBuf roff, slen, rbeg, rpre, rcode;
     DevBuf icount, ioff, iblock, is0;

@@ -696,13 +696,17 @@ __global__ void bfs_root_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
 
 // One level down: entries above the DFS level that are not inside are
 // replaced by their passing children; the others are carried unchanged.
+// The count pass keeps each opened entry's child tests (passing children in
+// the low byte, inside children in the next) in cmask, and the fill pass
+// reads them back instead of testing the child boxes again.
 template <bool FILL>
 __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
                                  const IBox* __restrict__ nodes, const IBox* __restrict__ bbox,
                                  const int32_t* __restrict__ bboxid, const FEntry* __restrict__ in,
                                  const int64_t* __restrict__ F_in, int64_t cap_in, int stop,
                                  int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                 FEntry* __restrict__ out, int64_t cap_out, MonoDev mono) {
+                                 FEntry* __restrict__ out, int64_t cap_out, MonoDev mono,
+                                 uint16_t* __restrict__ cmask) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= cap_in) return;
     if (e >= *F_in) {
@@ -725,11 +729,15 @@ __global__ void bfs_level_kernel(BatchDev bd, const TreeView* __restrict__ tvs,
     int s[3];
     decode_shift(E.sc, s);
     uint32_t pass, inside;
-    expand2(tvs[x], nodes, E.lev, E.node, bbox[E.blk], s, bd.box[x].W, bd.box[x].T, pass, inside);
     if (!FILL) {
+        expand2(tvs[x], nodes, E.lev, E.node, bbox[E.blk], s, bd.box[x].W, bd.box[x].T, pass, inside);
         cnt[e] = __popc(pass);
+        cmask[e] = (uint16_t)(pass | (inside << 8));
         return;
     }
+    const uint32_t m = cmask[e];
+    pass = m & 0xffu;
+    inside = m >> 8;
     int64_t o = off[e];
     while (pass) {
         const int c = __builtin_ctz(pass);
@@ -1335,6 +1343,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
     PP_TRY(w.fent_b.reserve(sizeof(FEntry) * (cap_b + 1)));
     PP_TRY(w.fcnt.reserve(sizeof(int32_t) * (capcnt + 1)));
     PP_TRY(w.foff.reserve(sizeof(int64_t) * (capcnt + 2)));
+    PP_TRY(w.fmask.reserve(sizeof(uint16_t) * (capcnt + 1)));
     hipLaunchKernelGGL(bfs_root_kernel<false>, dim3(blocks_for(cb, 128)), dim3(128), 0, s, bd, tvs,
                        nodes, bbox, bboxid, (const int64_t*)sizes, cb, w.fcnt.as<int32_t>(),
                        (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
@@ -1356,7 +1365,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         hipLaunchKernelGGL(bfs_level_kernel<false>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd,
                            tvs, nodes, bbox, bboxid, cur->as<FEntry>(),
                            (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, w.fcnt.as<int32_t>(),
-                           (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono);
+                           (const int64_t*)nullptr, (FEntry*)nullptr, (int64_t)0, mono, w.fmask.as<uint16_t>());
         PP_HIP(hipGetLastError());
         const ScanNote note{(int)(kEntry0 + p), (int)(kNeedEntry0 + p), cout, 2ull,
                             p == npass - 1 ? (int)kNEntry : -1};
@@ -1365,7 +1374,7 @@ int stage_lists(const BatchDev& bd, const std::vector<int64_t>& poff, int chunk_
         hipLaunchKernelGGL(bfs_level_kernel<true>, dim3(blocks_for(cin, 128)), dim3(128), 0, s, bd, tvs,
                            nodes, bbox, bboxid, cur->as<FEntry>(),
                            (const int64_t*)(sizes + kEntry0 + p - 1), cin, stop, (int32_t*)nullptr,
-                           w.foff.as<int64_t>(), nxt->as<FEntry>(), cout, mono);
+                           w.foff.as<int64_t>(), nxt->as<FEntry>(), cout, mono, w.fmask.as<uint16_t>());
         PP_HIP(hipGetLastError());
         DevBuf* t = cur;
         cur = nxt;
