@@ -46,48 +46,48 @@ TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "143cd8c9b94ff504b62c1457abf9209b6ac724fd",
+    "sha1": "65e42ff5f09c6511ae813820cdd2efaa2bc0b645",
     "fetch_scale": 1.99996,       # 1 GiB copy: 1048576 KiB / 524299.5 KiB of FETCH_SIZE
     "write_scale": 1.00000,       # 1 GiB copy: 1048576 KiB / 1048576.0 KiB of WRITE_SIZE
     # (chunk, waves per block, waves per CU (0: one workgroup per item), persistent):
     # (FETCH_SIZE KiB, WRITE_SIZE KiB) of the timed step's PP dispatch
     "kib": {
-        (1024, 1, 0, 0): (98476.3, 183744.5),
-        (1024, 1, 12, 1): (127413.8, 177636.7),
-        (1024, 1, 20, 1): (143044.9, 178276.7),
-        (1024, 1, 24, 1): (163171.4, 178596.7),
-        (1024, 1, 32, 1): (163015.5, 179108.7),
-        (2048, 1, 0, 0): (104940.9, 108831.7),
-        (2048, 1, 12, 1): (137537.7, 106031.5),
-        (2048, 1, 20, 1): (182690.5, 106655.2),
-        (2048, 1, 24, 1): (207819.6, 106968.6),
-        (2048, 1, 32, 1): (210948.6, 107481.4),
-        (2048, 2, 20, 1): (138990.2, 106033.6),
-        (2048, 2, 24, 1): (138700.9, 106158.6),
-        (2048, 2, 32, 1): (137671.8, 106415.8),
-        (4096, 1, 20, 1): (319110.7, 137895.2),
-        (4096, 1, 32, 1): (364703.8, 138528.6),
-        (4096, 2, 20, 1): (201089.8, 137850.3),
-        (4096, 2, 24, 1): (200960.1, 137957.4),
-        (4096, 2, 32, 1): (198581.8, 138201.0),
-        (4096, 4, 0, 0): (107042.4, 152060.0),
-        (4096, 4, 12, 1): (142220.3, 137529.4),
-        (4096, 4, 20, 1): (153249.3, 137807.9),
-        (4096, 4, 24, 1): (153924.6, 137868.4),
-        (4096, 4, 32, 1): (152608.2, 137994.1),
-        (8192, 2, 32, 1): (265121.8, 180833.6),
-        (8192, 4, 0, 0): (117593.1, 190445.6),
-        (8192, 4, 12, 1): (155755.4, 180853.3),
-        (8192, 4, 20, 1): (188127.8, 180865.5),
-        (8192, 4, 24, 1): (187394.6, 180913.2),
-        (8192, 4, 32, 1): (187550.4, 181053.9),
-        (8192, 8, 20, 1): (153673.8, 180869.8),
-        (8192, 8, 32, 1): (155178.2, 180953.8),
-        (16384, 4, 20, 1): (198121.1, 195508.1),
-        (16384, 4, 24, 1): (197856.8, 195580.6),
-        (16384, 4, 32, 1): (197927.6, 195678.9),
-        (16384, 8, 20, 1): (161966.4, 195590.5),
-        (16384, 8, 32, 1): (161105.2, 195654.8),
+        (1024, 1, 0, 0): (98508.5, 183744.5),
+        (1024, 1, 12, 1): (125898.2, 177636.7),
+        (1024, 1, 20, 1): (146260.6, 178276.7),
+        (1024, 1, 24, 1): (164353.3, 178596.7),
+        (1024, 1, 32, 1): (162324.5, 179108.7),
+        (2048, 1, 0, 0): (105528.3, 108829.9),
+        (2048, 1, 12, 1): (140234.6, 106034.8),
+        (2048, 1, 20, 1): (186092.7, 106656.2),
+        (2048, 1, 24, 1): (211390.6, 106965.2),
+        (2048, 1, 32, 1): (211354.8, 107477.7),
+        (2048, 2, 20, 1): (139695.2, 106031.5),
+        (2048, 2, 24, 1): (139916.9, 106156.1),
+        (2048, 2, 32, 1): (137368.6, 106416.7),
+        (4096, 1, 20, 1): (310858.3, 137882.4),
+        (4096, 1, 32, 1): (365708.2, 138533.8),
+        (4096, 2, 20, 1): (201871.1, 137840.6),
+        (4096, 2, 24, 1): (199949.9, 137962.2),
+        (4096, 2, 32, 1): (202702.9, 138224.7),
+        (4096, 4, 0, 0): (107140.8, 152063.1),
+        (4096, 4, 12, 1): (141256.6, 137574.5),
+        (4096, 4, 20, 1): (152858.9, 137806.2),
+        (4096, 4, 24, 1): (152999.6, 137875.5),
+        (4096, 4, 32, 1): (153520.7, 137999.6),
+        (8192, 2, 32, 1): (264249.4, 180883.7),
+        (8192, 4, 0, 0): (117253.4, 190447.5),
+        (8192, 4, 12, 1): (153192.7, 180898.8),
+        (8192, 4, 20, 1): (186151.2, 180916.6),
+        (8192, 4, 24, 1): (186111.5, 180942.6),
+        (8192, 4, 32, 1): (186622.2, 181113.0),
+        (8192, 8, 20, 1): (154129.4, 180899.1),
+        (8192, 8, 32, 1): (151935.3, 180978.5),
+        (16384, 4, 20, 1): (195679.2, 195550.9),
+        (16384, 4, 24, 1): (198638.8, 195604.2),
+        (16384, 4, 32, 1): (198745.4, 195723.9),
+        (16384, 8, 20, 1): (160202.6, 195599.1),
+        (16384, 8, 32, 1): (160010.7, 195668.2),
     },
 }
 
