@@ -144,9 +144,8 @@ constexpr HCoef kHC = make_hcoef();
 
 // (U_max/2)^{3/2} H(u) at r2 = s_eps^2 / ell^2: the polynomial in t = r2 - 1
 // (Horner, one FMA per degree), or (TABLE) the interpolated table of the
-// paper's design: kTabN
-// quadratic pieces over r2 in [0, 2), each stored as (a, b, c) with
-// h = a + z (b + z c), z the position inside the piece.  Past r2 = 2 the
+// paper's design: kTabN quadratic pieces over r2 in [0, 2), each stored as
+// (a, b, c) with h = a + z (b + z c), z the position inside the piece.  Past r2 = 2 the
 // last piece is extrapolated; such pairs lie beyond the cut and are masked.
 constexpr int kTabN = 128;
 
@@ -214,9 +213,10 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
     s = t;
 }
 
-// Orders this wave's LDS accesses around a point (the workgroup is one
-// wave, and a wave's LDS operations complete in issue order, so no
-// s_barrier is needed).
+// Orders this wave's LDS accesses around a point.  Every caller works on
+// LDS that only its own wave touches (a workgroup of K waves gives each wave
+// its own slices), and a wave's LDS operations complete in issue order, so
+// no s_barrier is needed.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -658,9 +658,10 @@ __global__ void __launch_bounds__(64) monopole_kernel(ItemArgs ia, const FEntry*
 }
 
 // One workgroup per item.
-// Both forms are bounded to 80 VGPRs (6 waves per SIMD): two waves' VALU
-// instructions can issue in the same cycle, so more resident waves keep the
-// pair loop's issue slots fuller.
+// Both forms are bounded to 6 waves per SIMD (80 VGPRs) with one wave per
+// block and to 5 with more: two waves' VALU instructions can issue in the
+// same cycle, so more resident waves keep the pair loop's issue slots
+// fuller.
 template <int VAR, int K>
 __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_kernel(ItemArgs ia, const double* __restrict__ pos_s,
                                                         const float* __restrict__ mass_s, int64_t N,
