@@ -42,13 +42,14 @@ FP32_VECTOR_PEAK = 157.3e12           # MI355X, 256 CU x 2.4 GHz x 256 flop/clk
 # per launch shape the autotuner is likely to pick.  Valid only for the
 # kernel sources they were taken on (SHA-1 over the files listed) and for a
 # measured launch shape; otherwise the roofline reports null.  The SHA-1 is
-# moved forward only over edits to comments, after comparing the gfx950
-# code objects built before and after (text, kernel descriptors, metadata).
+# moved forward only over edits that leave the machine code and metadata of
+# every kernel already built identical (compared function by function in the
+# gfx950 code objects built before and after).
 TRAFFIC = {
     "sources": ["paper_1802_09824_amd/csrc/pp_kernels.hip",
                 "paper_1802_09824_amd/csrc/pp_internal.h",
                 "paper_1802_09824_amd/csrc/tree.hip"],
-    "sha1": "c550e86369af3ea61fdf7147489bc799ebcd9d59",
+    "sha1": "720ab4d49720f40a153c28a79d3c85e7edaf4e64",
     "fetch_scale": 1.99996,       # 1 GiB copy: 1048576 KiB / 524299.5 KiB of FETCH_SIZE
     "write_scale": 1.00000,       # 1 GiB copy: 1048576 KiB / 1048576.0 KiB of WRITE_SIZE
     # (chunk, waves per block, waves per CU (0: one workgroup per item), persistent):

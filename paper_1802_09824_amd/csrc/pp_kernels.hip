@@ -688,6 +688,37 @@ __global__ void __launch_bounds__(64 * K, K > 1 ? 5 : 6) pp_f32_kernel(ItemArgs 
     }
 }
 
+// The same for launches of at most two waves per SIMD (short item lists,
+// small boxes): compiled for two resident waves, so the register budget
+// lets the compiler keep more of the unrolled sweep's pairs in flight, which
+// a SIMD with only two waves to issue from needs.  Same arithmetic in the
+// same order, so the same results.
+template <int VAR, int K>
+__global__ void __launch_bounds__(64 * K, 2) pp_f32_kernel_few(ItemArgs ia, const double* __restrict__ pos_s,
+                                                               const float* __restrict__ mass_s, int64_t N,
+                                                               float* __restrict__ partial,
+                                                               unsigned long long* __restrict__ counters) {
+    __shared__ float4 tile[K * 2 * kBlock];
+    __shared__ float4 qb[K * 8];
+    __shared__ double red[K > 1 ? K * 3 * kBlock : 1];
+    __shared__ float4 tab[(VAR & 8) ? kTabN : 1];
+    __shared__ int mark[K * kBlock];
+    if (ia.sizes[kSkip]) return;
+    const int64_t nitem = ia.sizes[kNItem];
+    const int64_t item = xcd_item(blockIdx.x, nitem);
+    if (item < 0) return;
+    if (VAR & 8) {
+        for (int k = threadIdx.x; k < kTabN; k += 64 * K) tab[k] = ia.split_tab[k];
+        __syncthreads();
+    }
+    unsigned long long n_eval = 0, n_lane = 0;
+    pp_item<VAR, K>(ia, item, pos_s, mass_s, N, partial, n_eval, n_lane, tile, tab, qb, red, mark);
+    if (counters && (threadIdx.x & (kBlock - 1)) == 0) {
+        atomicAdd(counters, n_eval);
+        atomicAdd(counters + 1, n_lane);
+    }
+}
+
 // Persistent form: a fixed grid of waves pulls items from 8 queues (one
 // contiguous stretch of items per XCD, as above); a wave first drains the
 // queue of its own XCD, then steals from the others.  Every wave leaves
@@ -1012,8 +1043,21 @@ static int launch_pp_f32_var(const ItemArgs& ia, const Work& w, Mode mode, int w
         // the device; the workgroups past it return at once)
         const int64_t per = (w.cap_item + 7) / 8;
         if (per == 0) return PP_OK;
-        hipLaunchKernelGGL((pp_f32_kernel<VAR, K>), dim3((unsigned)(per * 8)), dim3(kBlock * K), 0, s,
-                           ia, w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters);
+        // At most two waves per SIMD by the last call's item count (a hint
+        // only: both forms give the same results), the form built for that.
+        bool few = false;
+        if constexpr (VAR == 0 || VAR == 8) {
+            int dev = 0, cus = 256;
+            PP_HIP(hipGetDevice(&dev));
+            PP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            few = w.nitem > 0 && w.nitem * K <= 2 * 4 * (int64_t)cus;
+            if (few)
+                hipLaunchKernelGGL((pp_f32_kernel_few<VAR, K>), dim3((unsigned)(per * 8)), dim3(kBlock * K), 0,
+                                   s, ia, w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters);
+        }
+        if (!few)
+            hipLaunchKernelGGL((pp_f32_kernel<VAR, K>), dim3((unsigned)(per * 8)), dim3(kBlock * K), 0, s,
+                               ia, w.pos_s.as<double>(), w.mass_s.as<float>(), w.pos_n, partial, counters);
     }
     PP_HIP(hipGetLastError());
     return PP_OK;

@@ -246,6 +246,28 @@ def test_edge_cases_several_waves_per_block(pp, oracle_mod, case, k):
     assert s["robust_max"] <= parity.ROBUST_MAX, (case, k, s)
 
 
+@pytest.mark.parametrize("k", [1, 4])
+def test_grid_launch_forms_agree_on_small_box(pp, oracle_mod, k):
+    """One workgroup per item on the 32 k uniform box.  A fresh plan's first
+    call knows no item count yet and launches the form built for many
+    resident waves; the next call sees few enough items (at most two waves
+    per SIMD of the 256-CU MI355X) and launches the form built for two.  Both
+    run the same arithmetic in the same order: the results must be
+    bit-identical and meet the oracle bars."""
+    b = W.make_config(1)
+    plan = pp.Plan(b.params, b.n)
+    plan.set_tuning(chunk=2048 * k, waves_per_block=k, persistent=0, waves_per_cu=20, use_graph=0)
+    pos, mass = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
+    first = plan.accel(pos, mass).cpu().numpy()
+    assert plan.stats()["nitem"] * k <= 2 * 4 * 256
+    later = plan.accel(pos, mass).cpu().numpy()
+    assert np.array_equal(first.view(np.uint32), later.view(np.uint32))
+    t = np.sort(np.random.default_rng(5).choice(b.n, 512, replace=False))
+    ref = oracle_mod.accel(b.pos, b.mass.astype(np.float64), b.params, targets=t, pair_abs=True)
+    s = parity.summary(later[:, t], ref)
+    assert s["median"] <= 1e-6 and s["p999"] <= 1e-4, s
+
+
 def test_rejects_nonfinite(pp):
     p = BoxParams(L=10.0, rs=1.0, rcut=4.5, eps=0.01)
     pos = np.random.default_rng(0).random((3, 100)) * 10
