@@ -255,9 +255,11 @@ int pp_plan_set_timing(pp_plan* plan, int on);
 
 /* Launch shape of the FP32 PP kernel.
  *  chunk        source-list positions per work item (multiple of 64)
- *  persistent   0: one workgroup per work item; 1: a fixed grid of
- *               waves_per_cu waves per CU pulling items from per-XCD queues
- *               with stealing
+ *  persistent   0: one workgroup per work item (when the previous call's
+ *               items give at most two waves per SIMD, a build of the
+ *               kernel for two resident waves; same results); 1: a fixed
+ *               grid of waves_per_cu waves per CU pulling items from
+ *               per-XCD queues with stealing
  *  waves_per_cu used by the persistent form, 1..64
  *  use_graph    1: capture the persistent kernel and the reduction in a
  *               hipGraph once and replay it (needs persistent = 1)
