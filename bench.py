@@ -659,8 +659,15 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     value = interactions * args.steps / elapsed
     k_ms = float(np.mean(kernel_ms))
-    kname = ("pp_f32_persistent" if tuning["persistent"] else "pp_f32_kernel") + \
-        f"<{tuning['variant']}, {tuning['waves_per_block']}>"
+    if tuning["persistent"]:
+        kname = "pp_f32_persistent"
+    else:
+        # the one-workgroup-per-item launch takes its two-wave build when the
+        # items give at most two waves per SIMD
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        few = tuning["variant"] in (0, 8) and int(st["nitem"]) * tuning["waves_per_block"] <= 2 * 4 * cus
+        kname = "pp_f32_kernel_few" if few else "pp_f32_kernel"
+    kname += f"<{tuning['variant']}, {tuning['waves_per_block']}>"
     equal_mass = bool(np.all(box.mass == box.mass[0]))
     flops = FLOPS_EQUAL_MASS if equal_mass else FLOPS_GENERAL
     achieved = interactions * flops / (k_ms * 1e-3)
