@@ -246,8 +246,8 @@ def test_edge_cases_several_waves_per_block(pp, oracle_mod, case, k):
     assert s["robust_max"] <= parity.ROBUST_MAX, (case, k, s)
 
 
-@pytest.mark.parametrize("k", [1, 4])
-def test_grid_launch_forms_agree_on_small_box(pp, oracle_mod, k):
+@pytest.mark.parametrize("k,variant", [(1, 0), (2, 0), (4, 0), (4, 8)])
+def test_grid_launch_forms_agree_on_small_box(pp, oracle_mod, k, variant):
     """One workgroup per item on the 32 k uniform box.  A fresh plan's first
     call knows no item count yet and launches the form built for many
     resident waves; the next call sees few enough items (at most two waves
@@ -256,7 +256,8 @@ def test_grid_launch_forms_agree_on_small_box(pp, oracle_mod, k):
     bit-identical and meet the oracle bars."""
     b = W.make_config(1)
     plan = pp.Plan(b.params, b.n)
-    plan.set_tuning(chunk=2048 * k, waves_per_block=k, persistent=0, waves_per_cu=20, use_graph=0)
+    plan.set_tuning(chunk=2048 * k, waves_per_block=k, persistent=0, waves_per_cu=20, use_graph=0,
+                    variant=variant)
     pos, mass = dev(b.pos, torch.float64), dev(b.mass, torch.float32)
     first = plan.accel(pos, mass).cpu().numpy()
     assert plan.stats()["nitem"] * k <= 2 * 4 * 256
